@@ -1,0 +1,173 @@
+/*
+ * mpts -- multiple-precision Taylor series integrator for the Lorenz system
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The method is the N-th order Taylor series method of Dimova et al.,
+ * "OpenMP parallelization of multiple precision Taylor series method":
+ *   - the Lorenz system, equation (1) (Section 2), parameters sigma, R, b;
+ *   - the Taylor step x_{n+1} = x_n + sum_{i=1}^N alpha_i tau^i, equation (2),
+ *     evaluated by Horner's rule (Section 2);
+ *   - the Taylor coefficients from the Leibniz recursion, equation (3), whose
+ *     two Cauchy-product sums are the reduction the paper parallelises
+ *     (Section 2, last paragraph; Section 4).
+ *
+ * Numbers: binary floating point with p = 32*L bits of mantissa, L 32-bit
+ * limbs.  Precision from decimal digits K: L = 2*ceil(ceil(K*log2(10))/64).
+ * Rounding is round-to-nearest, ties-to-even, at these points only: each
+ * Cauchy sum (exact sum of exact products, rounded once), each new
+ * coefficient (exact numerator divided by i+1, rounded once), each Horner
+ * step h <- h*tau + c_i (rounded once).  Results therefore do not depend on
+ * how the GPU orders or splits the reductions.
+ *
+ * Conventions for every call:
+ *   - returns MPTS_OK (0) or a negative MPTS_E* code; no exception or abort
+ *     crosses this interface;
+ *   - host buffers are owned by the caller; the library owns only the
+ *     context; all device memory is a caller-provided workspace
+ *     (mpts_workspace_bytes) and device state buffers (mpts_state_bytes);
+ *   - `stream` is a hipStream_t (NULL = default stream); calls are
+ *     stream-ordered; the host-buffer variants synchronise before returning;
+ *   - a context is not thread-safe: use one context per host thread/stream.
+ */
+#ifndef MPTS_H
+#define MPTS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPTS_OK 0
+#define MPTS_EINVAL (-1)       /* null pointer, bad string, K<1, N<1, nsteps<0, ... */
+#define MPTS_ENOSPC (-2)       /* workspace smaller than mpts_workspace_bytes */
+#define MPTS_EHIP (-3)         /* HIP runtime error (see mpts_last_error) */
+#define MPTS_ERANGE (-4)       /* an exact sum spread over more than the device
+                                  window (see MPTS_MAX_SPREAD_BITS) or an
+                                  exponent left the int32 range */
+#define MPTS_EARCH (-5)        /* the current device is not gfx950 */
+#define MPTS_EUNSUPPORTED (-6) /* size beyond the compiled limits */
+
+/* Largest exponent difference (in bits) between the terms of one exact
+ * sum that the device accumulators hold; beyond it a call fails with
+ * MPTS_ERANGE instead of returning an inexact result. */
+#define MPTS_MAX_SPREAD_BITS 448
+
+/* flags for mpts_integrate / mpts_integrate_batch */
+#define MPTS_CHECKPOINTS 1u    /* keep every per-step state (see checkpoints) */
+#define MPTS_GRAPH 2u          /* batch: capture the launch in a hipGraph and replay it */
+#define MPTS_AUTOTUNE 4u       /* batch: measure schedules before the run */
+
+typedef struct mpts_ctx mpts_ctx;
+
+/* A big-float: value = sign * M * 2^exp with M = sum_j limbs[j] * 2^(32 j),
+ * j = 0..L-1, and the top bit of limbs[L-1] set; sign is -1, 0 or +1 and a
+ * zero has sign 0 (limbs all 0, exp 0).  `limbs` points to L caller-owned
+ * uint32_t. */
+typedef struct {
+  int32_t sign;
+  int32_t exp;
+  uint32_t *limbs;
+} mpts_bf;
+
+/* Problem definition (equation (1) parameters, Taylor order N of equation
+ * (2), step tau).  sigma, R, b, tau are exact decimal ("-15.8", "1e-2") or
+ * rational ("8/3") strings, each rounded once to p bits.  K_digits >= 1 sets
+ * the precision (L from the rule above); 1 <= N <= 8192.
+ * Errors: MPTS_EINVAL (bad argument), MPTS_EARCH, MPTS_EHIP. */
+int mpts_create(const char *sigma, const char *R, const char *b,
+                int32_t K_digits, int32_t N, const char *tau, mpts_ctx **out);
+
+/* As mpts_create with the limb count L (1 <= L <= 1024) given directly. */
+int mpts_create_limbs(const char *sigma, const char *R, const char *b,
+                      int32_t L, int32_t N, const char *tau, mpts_ctx **out);
+
+void mpts_destroy(mpts_ctx *ctx);
+
+/* L, p = 32 L and N of a context (any pointer may be NULL). */
+int mpts_limbs(const mpts_ctx *ctx, int32_t *L, int32_t *p_bits, int32_t *N);
+
+/* The rounded parameters: which = 0 sigma, 1 R, 2 b, 3 tau. */
+int mpts_param(const mpts_ctx *ctx, int32_t which, mpts_bf *out);
+
+/* Exact parse of a decimal or rational string, one rounding to p bits. */
+int mpts_bf_from_str(const mpts_ctx *ctx, const char *s, mpts_bf *out);
+/* A double, rounded to p bits (exact when p >= 53). */
+int mpts_bf_from_double(const mpts_ctx *ctx, double v, mpts_bf *out);
+/* Nearest double (RNE); |v| beyond the double range gives +-inf. */
+int mpts_bf_to_double(const mpts_ctx *ctx, const mpts_bf *v, double *out);
+
+/* Workgroups per trajectory for single-trajectory calls (0 = automatic,
+ * the number of compute units).  Results do not depend on it. */
+int mpts_set_schedule(mpts_ctx *ctx, int32_t workgroups);
+
+/* Device workspace needed by mpts_integrate*, mpts_coefficients and
+ * mpts_grad for `nsteps` steps. */
+int mpts_workspace_bytes(const mpts_ctx *ctx, int64_t nsteps, uint32_t flags,
+                         size_t *bytes);
+
+/* Bytes of one device state (3 components) in the packed device format
+ * [sign, exp, limbs[L]] x 3, int32 words. */
+int mpts_state_bytes(const mpts_ctx *ctx, size_t *bytes);
+/* Host-side packing of x[3] into / out of that format. */
+int mpts_pack_state(const mpts_ctx *ctx, const mpts_bf x[3], void *packed);
+int mpts_unpack_state(const mpts_ctx *ctx, const void *packed, mpts_bf x[3]);
+
+/* `nsteps` Taylor steps (equation (2)) from x0 (host); the final state is
+ * written to x_out (host).  With checkpoints != NULL it receives the
+ * 3*(nsteps+1) states s_0..s_nsteps (each with L limbs of storage).
+ * Synchronises `stream`.  MPTS_ERANGE is returned if any exact sum did not
+ * fit the device window (the outputs are then undefined). */
+int mpts_integrate(mpts_ctx *ctx, const mpts_bf x0[3], int64_t nsteps,
+                   mpts_bf x_out[3], mpts_bf *checkpoints, void *workspace,
+                   size_t ws_bytes, void *stream, uint32_t flags);
+
+/* Device-resident variant, asynchronous on `stream`: x0_dev and xout_dev are
+ * packed device states, ckpt_dev (may be NULL) receives nsteps+1 packed
+ * states.  Errors found on the device are reported by mpts_check. */
+int mpts_integrate_dev(mpts_ctx *ctx, const void *x0_dev, int64_t nsteps,
+                       void *xout_dev, void *ckpt_dev, void *workspace,
+                       size_t ws_bytes, void *stream);
+
+/* Synchronises `stream` and returns the device error status recorded in
+ * the workspace by the last call (MPTS_OK or MPTS_ERANGE). */
+int mpts_check(mpts_ctx *ctx, void *workspace, void *stream);
+
+/* The Taylor coefficients alpha_i, beta_i, gamma_i, i = 0..N (equation (3))
+ * of one step from x0, each N+1 arrays of caller-owned mpts_bf (L limbs). */
+int mpts_coefficients(mpts_ctx *ctx, const mpts_bf x0[3], mpts_bf *alpha,
+                      mpts_bf *beta, mpts_bf *gamma, void *workspace,
+                      size_t ws_bytes, void *stream);
+
+/* Batched ensemble: `count` trajectories, trajectory t with its own context
+ * ctxs[t] (its own K, N), initial state x0[3t..3t+2], nsteps[t] steps, final
+ * state into x_out[3t..3t+2].  All run in one persistent launch; with
+ * MPTS_GRAPH the launch is captured in a hipGraph and replayed.  The device
+ * workspace size comes from mpts_batch_workspace_bytes. */
+int mpts_batch_workspace_bytes(mpts_ctx *const *ctxs, int32_t count,
+                               const int64_t *nsteps, uint32_t flags,
+                               size_t *bytes);
+int mpts_integrate_batch(mpts_ctx *const *ctxs, int32_t count,
+                         const mpts_bf *x0, const int64_t *nsteps,
+                         mpts_bf *x_out, void *workspace, size_t ws_bytes,
+                         void *stream, uint32_t flags);
+
+/* Gradient of the loss ||x(T)||^2, T = nsteps*tau, with respect to
+ * (x0, y0, z0, sigma, R, b) by a hand-written reverse sweep in the same
+ * p-bit arithmetic: per-step states are checkpointed by a forward run and
+ * the coefficients are recomputed per step.  grad_out receives 6 doubles
+ * (each the RNE of the p-bit result); grad_bf (may be NULL) receives the 6
+ * p-bit values; x_out (may be NULL) the final state. */
+int mpts_grad(mpts_ctx *ctx, const mpts_bf x0[3], int64_t nsteps,
+              double grad_out[6], mpts_bf *grad_bf, mpts_bf x_out[3],
+              void *workspace, size_t ws_bytes, void *stream);
+
+const char *mpts_strerror(int status);
+/* Text of the last error recorded on this context ("" if none). */
+const char *mpts_last_error(const mpts_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPTS_H */

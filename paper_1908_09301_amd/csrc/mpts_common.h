@@ -1,0 +1,61 @@
+// Shared layout constants and the device-side trajectory descriptor.
+//
+// Product digits.  Every Taylor coefficient that enters a product is stored
+// as a "row": the exact value s * D * 2^(28 e) with D split into nd signed
+// radix-2^28 digits that all carry the sign s (digit j has weight 2^(28(e+j))).
+// A product of two rows is then a sum of 32x32 -> 64-bit signed digit products
+// (v_mad_i64_i32) with no sign handling, and a sum of products of rows with
+// different exponents is a sum of shifted digit convolutions.
+//
+// Row layout (int32 words): [HDR header: e, s, 0...][RPAD zero digits]
+// [nd digits][RPAD + TQ zero digits], stride RS rounded to 32 words (128 B).
+#pragma once
+#include <stdint.h>
+
+namespace mpts {
+
+constexpr int DBITS = 28;                      // bits per product digit
+constexpr long long DMASK = (1LL << DBITS) - 1;
+constexpr int TQ = 8;                          // tile edge in digits (8x8 products per lane)
+constexpr int WGS = 256;                       // threads per workgroup
+constexpr int SMAX = 16;                       // largest exponent spread (digits) of one exact sum
+constexpr int HDR = 8;                         // row header words
+constexpr int RPAD = 24;                       // zero digits on each side of a row
+constexpr int NFR = 5;                         // product frames per coefficient index
+constexpr int FLUSH_TERMS = 15;                // terms between accumulator carry-normalisations
+
+// constant rows (each a p-bit value converted to a row at kernel start)
+enum { C_SIGMA = 0, C_NSIGMA, C_R, C_NB, C_TAU, C_ONE, NCONST };
+
+// sync words, each on its own 128-byte line
+enum { SY_ARRIVE = 0, SY_FLAG = 32, SY_ERROR = 64, SY_WORDS = 96 };
+
+enum { MODE_INTEGRATE = 0, MODE_COEFFS = 1, MODE_ADJOINT = 2 };
+
+inline int digits_per_row(int L) { return (32 * L + DBITS - 1 + DBITS - 1) / DBITS; }
+inline int row_stride(int nd) { int rs = HDR + RPAD + nd + RPAD + TQ; return (rs + 31) & ~31; }
+// frame width in columns: products of two rows span 2 nd - 1 columns, plus the
+// spread, plus the tile overhang of the last diagonal, plus carries.
+inline int frame_width(int nd) { int w = 2 * nd + SMAX + 2 * TQ + 8; return (w + 31) & ~31; }
+// digits one single-wave big-integer task must hold (combine + division)
+inline int task_digits(int nd) { return 3 * nd + 2 * SMAX + 48; }
+
+struct Inst {
+  int L, N, nd, RS, WB, CM;  // limbs, order, digits/row, row stride, frame width, chunk max
+  int G, wg0;                // workgroups of the group and the first one
+  int mode;
+  int pad0;
+  long long nsteps;
+  int32_t *rows;      // [3][N+1][RS]
+  int32_t *consts;    // [NCONST][RS]
+  int32_t *cnorm;     // [NCONST][L+2] normalised constants (written by the host)
+  int32_t *state;     // [3][L+2] normalised state (sign, E, M[L]), in and out
+  int32_t *coefs;     // [3][N+1][L+2] normalised coefficients (MODE_COEFFS) or null
+  int32_t *ckpt;      // [nsteps+1][3][L+2] or null
+  long long *gframes; // [2][NFR][WB] (G > 1)
+  uint32_t *sync;     // SY_* words
+  // adjoint
+  int32_t *adj;       // adjoint scratch (MODE_ADJOINT)
+};
+
+}  // namespace mpts

@@ -1,0 +1,725 @@
+// C ABI of the library: contexts, exact parsing and rounding of the
+// problem's numbers on the host, workspace layout, and the calls that run
+// the device kernels (include/mpts.h documents every entry point).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mpts.h"
+#include "mpts_common.h"
+#include "mpts_kernels.h"
+
+using namespace mpts;
+
+// ---------------------------------------------------------------------------
+// Host big integers (little-endian 32-bit words, no leading zero words).
+namespace {
+
+typedef std::vector<uint32_t> Big;
+
+void trim(Big &a) {
+  while (!a.empty() && a.back() == 0) a.pop_back();
+}
+
+long long bitlen(const Big &a) {
+  if (a.empty()) return 0;
+  uint32_t t = a.back();
+  int b = 0;
+  while (t) {
+    ++b;
+    t >>= 1;
+  }
+  return 32LL * (long long)(a.size() - 1) + b;
+}
+
+void mul_small_add(Big &a, uint32_t m, uint32_t add) {
+  uint64_t c = add;
+  for (auto &w : a) {
+    uint64_t t = (uint64_t)w * m + c;
+    w = (uint32_t)t;
+    c = t >> 32;
+  }
+  if (c) a.push_back((uint32_t)c);
+}
+
+Big shl(const Big &a, long long s) {
+  if (a.empty()) return a;
+  long long ws = s / 32;
+  int bs = (int)(s % 32);
+  Big r((size_t)ws, 0u);
+  uint32_t carry = 0;
+  for (uint32_t w : a) {
+    r.push_back((w << bs) | carry);
+    carry = bs ? (w >> (32 - bs)) : 0;
+  }
+  if (carry) r.push_back(carry);
+  trim(r);
+  return r;
+}
+
+int cmp(const Big &a, const Big &b) {
+  if (a.size() != b.size()) return a.size() < b.size() ? -1 : 1;
+  for (size_t i = a.size(); i-- > 0;)
+    if (a[i] != b[i]) return a[i] < b[i] ? -1 : 1;
+  return 0;
+}
+
+void sub_in(Big &a, const Big &b) {  // a -= b, a >= b
+  int64_t br = 0;
+  for (size_t i = 0; i < a.size(); ++i) {
+    int64_t t = (int64_t)a[i] - (i < b.size() ? b[i] : 0) - br;
+    br = t < 0;
+    a[i] = (uint32_t)(t + (br ? (1LL << 32) : 0));
+  }
+  trim(a);
+}
+
+bool get_bit(const Big &a, long long i) {
+  size_t w = (size_t)(i / 32);
+  return w < a.size() && ((a[w] >> (i % 32)) & 1u);
+}
+
+// floor(n / d) and n mod d by binary long division (d > 0)
+void divmod(const Big &n, const Big &d, Big &q, Big &r) {
+  q.assign((n.size()), 0u);
+  r.clear();
+  for (long long i = bitlen(n) - 1; i >= 0; --i) {
+    r = shl(r, 1);
+    if (get_bit(n, i)) {
+      if (r.empty()) r.push_back(1u);
+      else r[0] |= 1u;
+    }
+    if (cmp(r, d) >= 0) {
+      sub_in(r, d);
+      q[(size_t)(i / 32)] |= 1u << (i % 32);
+    }
+  }
+  trim(q);
+}
+
+struct Rational {
+  int neg = 0;
+  Big num, den;  // den > 0
+};
+
+Big pow10(long long e) {
+  Big r{1u};
+  for (long long i = 0; i < e; ++i) mul_small_add(r, 10u, 0u);
+  return r;
+}
+
+Big mul(const Big &a, const Big &b) {
+  if (a.empty() || b.empty()) return Big();
+  Big r(a.size() + b.size(), 0u);
+  for (size_t i = 0; i < a.size(); ++i) {
+    uint64_t c = 0;
+    for (size_t j = 0; j < b.size(); ++j) {
+      uint64_t t = (uint64_t)a[i] * b[j] + r[i + j] + c;
+      r[i + j] = (uint32_t)t;
+      c = t >> 32;
+    }
+    r[i + b.size()] += (uint32_t)c;
+  }
+  trim(r);
+  return r;
+}
+
+// decimal: [+-]digits[.digits][(e|E)[+-]digits]
+bool parse_decimal(const std::string &s, Rational &out) {
+  size_t i = 0;
+  out = Rational();
+  if (i < s.size() && (s[i] == '+' || s[i] == '-')) out.neg = s[i++] == '-';
+  bool any = false;
+  long long frac_digits = 0;
+  Big m;
+  while (i < s.size() && isdigit((unsigned char)s[i])) {
+    mul_small_add(m, 10, (uint32_t)(s[i++] - '0'));
+    any = true;
+  }
+  if (i < s.size() && s[i] == '.') {
+    ++i;
+    while (i < s.size() && isdigit((unsigned char)s[i])) {
+      mul_small_add(m, 10, (uint32_t)(s[i++] - '0'));
+      ++frac_digits;
+      any = true;
+    }
+  }
+  if (!any) return false;
+  long long ex = 0;
+  if (i < s.size() && (s[i] == 'e' || s[i] == 'E')) {
+    ++i;
+    int eneg = 0;
+    if (i < s.size() && (s[i] == '+' || s[i] == '-')) eneg = s[i++] == '-';
+    bool ed = false;
+    while (i < s.size() && isdigit((unsigned char)s[i])) {
+      ex = ex * 10 + (s[i++] - '0');
+      ed = true;
+      if (ex > 100000) return false;
+    }
+    if (!ed) return false;
+    if (eneg) ex = -ex;
+  }
+  if (i != s.size()) return false;
+  trim(m);
+  long long e10 = ex - frac_digits;
+  if (e10 >= 0) {
+    out.num = mul(m, pow10(e10));
+    out.den = Big{1u};
+  } else {
+    out.num = m;
+    out.den = pow10(-e10);
+  }
+  return true;
+}
+
+bool parse_number(const char *text, Rational &out) {
+  if (!text) return false;
+  std::string s(text);
+  s.erase(std::remove_if(s.begin(), s.end(), [](char c) { return isspace((unsigned char)c); }),
+          s.end());
+  size_t sl = s.find('/');
+  if (sl == std::string::npos) return parse_decimal(s, out);
+  Rational a, b;
+  if (!parse_decimal(s.substr(0, sl), a) || !parse_decimal(s.substr(sl + 1), b)) return false;
+  if (b.num.empty()) return false;
+  out.neg = a.neg ^ b.neg;
+  out.num = mul(a.num, b.den);
+  out.den = mul(a.den, b.num);
+  return true;
+}
+
+// Round (num/den) * 2^exp2 to p bits, ties to even, into [sign, E, M[L]].
+void round_rational(const Rational &q, long long exp2, int L, std::vector<int32_t> &nv) {
+  nv.assign((size_t)L + 2, 0);
+  if (q.num.empty()) return;
+  const long long p = 32LL * L;
+  long long k = p - (bitlen(q.num) - bitlen(q.den));
+  Big Q, R, D;
+  for (;;) {
+    Big n = q.num;
+    D = q.den;
+    if (k >= 0) n = shl(n, k);
+    else D = shl(D, -k);
+    divmod(n, D, Q, R);
+    long long b = bitlen(Q);
+    if (b > p) k -= 1;
+    else if (b < p) k += 1;
+    else break;
+  }
+  // round: compare 2R with D
+  Big R2 = shl(R, 1);
+  int c = cmp(R2, D);
+  bool up = c > 0 || (c == 0 && !Q.empty() && (Q[0] & 1u));
+  if (up) {
+    mul_small_add(Q, 1, 1);  // Q += 1
+    if (bitlen(Q) > p) {
+      Q = Big((size_t)L, 0u);
+      Q[L - 1] = 0x80000000u;
+      k -= 1;
+    }
+  }
+  Q.resize((size_t)L, 0u);
+  nv[0] = q.neg ? -1 : 1;
+  nv[1] = (int32_t)(exp2 - k);
+  for (int j = 0; j < L; ++j) nv[2 + j] = (int32_t)Q[j];
+}
+
+void negate_nv(std::vector<int32_t> &nv) { nv[0] = -nv[0]; }
+
+double nv_to_double(const int32_t *nv, int L) {
+  int s = nv[0];
+  if (s == 0) return 0.0;
+  long long E = nv[1];
+  const uint32_t *M = (const uint32_t *)(nv + 2);
+  long long top = E + 32LL * L - 1;  // exponent of the leading bit
+  int prec = 53;
+  if (top < -1022) prec = (int)(53 - (-1022 - top));
+  if (top > 1023) return s > 0 ? INFINITY : -INFINITY;
+  if (prec <= 0) {
+    // below half the smallest subnormal, or exactly around it
+    if (prec < 0) return s > 0 ? 0.0 : -0.0;
+    // prec == 0: value in [2^-1075, 2^-1074): rounds to 2^-1074 unless it is exactly the tie
+    bool rest = false;
+    for (int j = 0; j < L; ++j) rest |= (j == L - 1) ? (M[j] != 0x80000000u) : (M[j] != 0u);
+    double v = rest ? std::ldexp(1.0, -1074) : 0.0;
+    return s > 0 ? v : -v;
+  }
+  // take the top `prec` bits, round bit and sticky
+  long long nbits = 32LL * L;
+  long long drop = nbits - prec;  // bits below the kept mantissa
+  auto bit = [&](long long i) -> uint64_t {
+    return (i >= 0 && i < nbits) ? ((M[i / 32] >> (i % 32)) & 1u) : 0u;
+  };
+  uint64_t mant = 0;
+  for (int j = prec - 1; j >= 0; --j) mant = (mant << 1) | bit(drop + j);
+  bool rb = drop >= 1 ? bit(drop - 1) : false;
+  bool st = false;
+  for (long long i = 0; i < drop - 1; ++i)
+    if (bit(i)) {
+      st = true;
+      break;
+    }
+  if (rb && (st || (mant & 1u))) {
+    mant += 1;
+    if (mant >> prec) {
+      mant >>= 1;
+      drop += 1;
+    }
+  }
+  double v = std::ldexp((double)mant, (int)(E + drop));
+  return s > 0 ? v : -v;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+struct mpts_ctx {
+  int L, N, nd, RS, WB, CM;
+  std::vector<int32_t> cn;  // NCONST x (L+2) normalised constants
+  int wgs = 0;
+  int cus = 0;
+  int max_per_cu = 0;
+  size_t lds = 0;
+  std::string err;
+};
+
+namespace {
+
+int set_err(mpts_ctx *c, int code, const std::string &msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_err(mpts_ctx *c, hipError_t e, const char *where) {
+  return set_err(c, MPTS_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+int choose_cm(int nd) {
+  int need = task_digits(nd);
+  for (int cm : {4, 8, 16, 32})
+    if (64 * cm >= need) return cm;
+  return -1;
+}
+
+struct Layout {
+  size_t sync, cnorm, state, consts, rows, gframes, coefs, ckpt, inst, wgmap, total;
+};
+
+size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+constexpr int kMaxWG = 4096;
+
+Layout layout(const mpts_ctx *c, long long nsteps, bool ckpt, int nwg) {
+  Layout l;
+  size_t o = 0;
+  l.sync = o;
+  o = al(o + SY_WORDS * 4);
+  l.cnorm = o;
+  o = al(o + (size_t)NCONST * (c->L + 2) * 4);
+  l.state = o;
+  o = al(o + (size_t)3 * (c->L + 2) * 4);
+  l.consts = o;
+  o = al(o + (size_t)NCONST * c->RS * 4);
+  l.rows = o;
+  o = al(o + (size_t)3 * (c->N + 1) * c->RS * 4);
+  l.gframes = o;
+  o = al(o + (size_t)2 * NFR * c->WB * 8);
+  l.coefs = o;
+  o = al(o + (size_t)3 * (c->N + 1) * (c->L + 2) * 4);
+  l.inst = o;
+  o = al(o + sizeof(Inst));
+  l.wgmap = o;
+  o = al(o + (size_t)kMaxWG * 4);
+  l.ckpt = o;
+  if (ckpt) o = al(o + (size_t)(nsteps + 1) * 3 * (c->L + 2) * 4);
+  l.total = o;
+  (void)nwg;
+  return l;
+}
+
+int check_device(mpts_ctx *c) {
+  if (c->cus > 0) return MPTS_OK;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_err(c, e, "hipGetDevice");
+  hipDeviceProp_t pr;
+  e = hipGetDeviceProperties(&pr, dev);
+  if (e != hipSuccess) return hip_err(c, e, "hipGetDeviceProperties");
+  if (strncmp(pr.gcnArchName, "gfx950", 6) != 0)
+    return set_err(c, MPTS_EARCH, std::string("device is ") + pr.gcnArchName + ", need gfx950");
+  c->cus = pr.multiProcessorCount;
+  c->lds = lds_bytes(c->L, c->RS, c->WB, c->CM);
+  if (max_coresident(c->CM, c->lds, &c->max_per_cu) != 0 || c->max_per_cu < 1)
+    return set_err(c, MPTS_EUNSUPPORTED, "kernel does not fit one compute unit");
+  return MPTS_OK;
+}
+
+int bf_to_nv(const mpts_ctx *c, const mpts_bf &b, int32_t *nv) {
+  if (b.sign == 0) {
+    for (int j = 0; j < c->L + 2; ++j) nv[j] = 0;
+    return MPTS_OK;
+  }
+  if (!b.limbs || (b.sign != 1 && b.sign != -1)) return MPTS_EINVAL;
+  if (!(b.limbs[c->L - 1] & 0x80000000u)) return MPTS_EINVAL;
+  nv[0] = b.sign;
+  nv[1] = b.exp;
+  for (int j = 0; j < c->L; ++j) nv[2 + j] = (int32_t)b.limbs[j];
+  return MPTS_OK;
+}
+
+int nv_to_bf(const mpts_ctx *c, const int32_t *nv, mpts_bf *b) {
+  if (!b || !b->limbs) return MPTS_EINVAL;
+  b->sign = nv[0];
+  b->exp = nv[0] ? nv[1] : 0;
+  for (int j = 0; j < c->L; ++j) b->limbs[j] = (uint32_t)nv[2 + j];
+  return MPTS_OK;
+}
+
+int make_ctx(const char *sigma, const char *R, const char *b, int L, int N, const char *tau,
+             mpts_ctx **out) {
+  if (!out) return MPTS_EINVAL;
+  *out = nullptr;
+  if (L < 1 || L > 1024 || N < 1 || N > 8192) return MPTS_EINVAL;
+  Rational qs, qr, qb, qt;
+  if (!parse_number(sigma, qs) || !parse_number(R, qr) || !parse_number(b, qb) ||
+      !parse_number(tau, qt))
+    return MPTS_EINVAL;
+  mpts_ctx *c = new mpts_ctx();
+  c->L = L;
+  c->N = N;
+  c->nd = digits_per_row(L);
+  c->RS = row_stride(c->nd);
+  c->WB = frame_width(c->nd);
+  c->CM = choose_cm(c->nd);
+  if (c->CM < 0) {
+    delete c;
+    return MPTS_EUNSUPPORTED;
+  }
+  c->cn.assign((size_t)NCONST * (L + 2), 0);
+  std::vector<int32_t> nv;
+  auto put = [&](int idx, const std::vector<int32_t> &v) {
+    std::copy(v.begin(), v.end(), c->cn.begin() + (size_t)idx * (L + 2));
+  };
+  round_rational(qs, 0, L, nv);
+  put(C_SIGMA, nv);
+  negate_nv(nv);
+  put(C_NSIGMA, nv);
+  round_rational(qr, 0, L, nv);
+  put(C_R, nv);
+  round_rational(qb, 0, L, nv);
+  negate_nv(nv);
+  put(C_NB, nv);
+  round_rational(qt, 0, L, nv);
+  put(C_TAU, nv);
+  Rational one;
+  one.num = Big{1u};
+  one.den = Big{1u};
+  round_rational(one, 0, L, nv);
+  put(C_ONE, nv);
+  *out = c;
+  return MPTS_OK;
+}
+
+int run_single(mpts_ctx *c, int mode, long long nsteps, const void *x0_dev, void *xout_dev,
+               void *ckpt_dev, void *ws, size_t ws_bytes, hipStream_t s, bool x0_on_host,
+               const int32_t *x0_host) {
+  int dst = check_device(c);
+  if (dst != MPTS_OK) return dst;
+  int G = c->wgs > 0 ? c->wgs : c->cus;
+  G = std::min(G, c->cus * c->max_per_cu);
+  G = std::max(std::min(G, kMaxWG), 1);
+  Layout l = layout(c, nsteps, false, G);
+  if (ws_bytes < l.total) return set_err(c, MPTS_ENOSPC, "workspace too small");
+  char *base = (char *)ws;
+  hipError_t e;
+  e = launch_clear(base + l.sync, SY_WORDS * 4, s);
+  if (e != hipSuccess) return hip_err(c, e, "clear");
+  e = launch_clear(base + l.gframes, (size_t)2 * NFR * c->WB * 8, s);
+  if (e != hipSuccess) return hip_err(c, e, "clear");
+  e = launch_clear(base + l.rows, (size_t)3 * (c->N + 1) * c->RS * 4, s);
+  if (e != hipSuccess) return hip_err(c, e, "clear");
+  e = hipMemcpyAsync(base + l.cnorm, c->cn.data(), c->cn.size() * 4, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_err(c, e, "copy constants");
+  size_t sb = (size_t)3 * (c->L + 2) * 4;
+  if (x0_on_host) e = hipMemcpyAsync(base + l.state, x0_host, sb, hipMemcpyHostToDevice, s);
+  else e = hipMemcpyAsync(base + l.state, x0_dev, sb, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return hip_err(c, e, "copy state");
+  Inst I;
+  memset(&I, 0, sizeof(I));
+  I.L = c->L;
+  I.N = c->N;
+  I.nd = c->nd;
+  I.RS = c->RS;
+  I.WB = c->WB;
+  I.CM = c->CM;
+  I.G = G;
+  I.wg0 = 0;
+  I.mode = mode;
+  I.nsteps = nsteps;
+  I.rows = (int32_t *)(base + l.rows);
+  I.consts = (int32_t *)(base + l.consts);
+  I.cnorm = (int32_t *)(base + l.cnorm);
+  I.state = (int32_t *)(base + l.state);
+  I.coefs = mode == MODE_COEFFS ? (int32_t *)(base + l.coefs) : nullptr;
+  I.ckpt = (int32_t *)ckpt_dev;
+  I.gframes = (long long *)(base + l.gframes);
+  I.sync = (uint32_t *)(base + l.sync);
+  e = hipMemcpyAsync(base + l.inst, &I, sizeof(I), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_err(c, e, "copy descriptor");
+  e = launch_clear(base + l.wgmap, (size_t)G * 4, s);
+  if (e != hipSuccess) return hip_err(c, e, "clear");
+  e = launch_run((const Inst *)(base + l.inst), (const int *)(base + l.wgmap), G, c->CM, c->lds, s);
+  if (e != hipSuccess) return hip_err(c, e, "launch");
+  if (xout_dev) {
+    e = hipMemcpyAsync(xout_dev, base + l.state, sb, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_err(c, e, "copy state out");
+  }
+  return MPTS_OK;
+}
+
+int read_status(mpts_ctx *c, void *ws, hipStream_t s) {
+  Layout l = layout(c, 0, false, 1);
+  uint32_t w = 0;
+  hipError_t e = hipMemcpyAsync(&w, (char *)ws + l.sync + SY_ERROR * 4, 4, hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return hip_err(c, e, "read status");
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_err(c, e, "synchronize");
+  if (w & 4u) return set_err(c, MPTS_EHIP, "device synchronisation timed out");
+  if (w & 3u) return set_err(c, MPTS_ERANGE, "exact sum outside the device window or exponent overflow");
+  return MPTS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int mpts_create(const char *sigma, const char *R, const char *b, int32_t K_digits, int32_t N,
+                const char *tau, mpts_ctx **out) {
+  if (K_digits < 1 || K_digits > 9864) return MPTS_EINVAL;
+  // L = 2 ceil(ceil(K log2 10) / 64); ceil(K log2 10) is the bit length of 10^K
+  Big t = pow10(K_digits);
+  long long bits = bitlen(t);
+  int L = (int)(2 * ((bits + 63) / 64));
+  return make_ctx(sigma, R, b, L, N, tau, out);
+}
+
+int mpts_create_limbs(const char *sigma, const char *R, const char *b, int32_t L, int32_t N,
+                      const char *tau, mpts_ctx **out) {
+  return make_ctx(sigma, R, b, L, N, tau, out);
+}
+
+void mpts_destroy(mpts_ctx *ctx) { delete ctx; }
+
+int mpts_limbs(const mpts_ctx *c, int32_t *L, int32_t *p_bits, int32_t *N) {
+  if (!c) return MPTS_EINVAL;
+  if (L) *L = c->L;
+  if (p_bits) *p_bits = 32 * c->L;
+  if (N) *N = c->N;
+  return MPTS_OK;
+}
+
+int mpts_param(const mpts_ctx *c, int32_t which, mpts_bf *out) {
+  if (!c || !out || which < 0 || which > 3) return MPTS_EINVAL;
+  static const int idx[4] = {C_SIGMA, C_R, C_NB, C_TAU};
+  std::vector<int32_t> nv(c->cn.begin() + (size_t)idx[which] * (c->L + 2),
+                          c->cn.begin() + (size_t)(idx[which] + 1) * (c->L + 2));
+  if (which == 2) nv[0] = -nv[0];
+  return nv_to_bf(c, nv.data(), out);
+}
+
+int mpts_bf_from_str(const mpts_ctx *c, const char *s, mpts_bf *out) {
+  if (!c || !out) return MPTS_EINVAL;
+  Rational q;
+  if (!parse_number(s, q)) return MPTS_EINVAL;
+  std::vector<int32_t> nv;
+  round_rational(q, 0, c->L, nv);
+  return nv_to_bf(c, nv.data(), out);
+}
+
+int mpts_bf_from_double(const mpts_ctx *c, double v, mpts_bf *out) {
+  if (!c || !out || !std::isfinite(v)) return MPTS_EINVAL;
+  Rational q;
+  if (v != 0.0) {
+    int ex;
+    double m = std::frexp(std::fabs(v), &ex);  // v = m 2^ex, m in [0.5, 1)
+    uint64_t mi = (uint64_t)std::ldexp(m, 53);
+    q.neg = v < 0;
+    q.num = Big{(uint32_t)mi, (uint32_t)(mi >> 32)};
+    trim(q.num);
+    q.den = Big{1u};
+    std::vector<int32_t> nv;
+    round_rational(q, ex - 53, c->L, nv);
+    return nv_to_bf(c, nv.data(), out);
+  }
+  std::vector<int32_t> nv((size_t)c->L + 2, 0);
+  return nv_to_bf(c, nv.data(), out);
+}
+
+int mpts_bf_to_double(const mpts_ctx *c, const mpts_bf *v, double *out) {
+  if (!c || !v || !out) return MPTS_EINVAL;
+  std::vector<int32_t> nv((size_t)c->L + 2);
+  int st = bf_to_nv(c, *v, nv.data());
+  if (st) return st;
+  *out = nv_to_double(nv.data(), c->L);
+  return MPTS_OK;
+}
+
+int mpts_set_schedule(mpts_ctx *c, int32_t workgroups) {
+  if (!c || workgroups < 0) return MPTS_EINVAL;
+  c->wgs = workgroups;
+  return MPTS_OK;
+}
+
+int mpts_workspace_bytes(const mpts_ctx *c, int64_t nsteps, uint32_t flags, size_t *bytes) {
+  if (!c || !bytes || nsteps < 0) return MPTS_EINVAL;
+  *bytes = layout(c, nsteps, (flags & MPTS_CHECKPOINTS) != 0, kMaxWG).total;
+  return MPTS_OK;
+}
+
+int mpts_state_bytes(const mpts_ctx *c, size_t *bytes) {
+  if (!c || !bytes) return MPTS_EINVAL;
+  *bytes = (size_t)3 * (c->L + 2) * 4;
+  return MPTS_OK;
+}
+
+int mpts_pack_state(const mpts_ctx *c, const mpts_bf x[3], void *packed) {
+  if (!c || !x || !packed) return MPTS_EINVAL;
+  int32_t *p = (int32_t *)packed;
+  for (int k = 0; k < 3; ++k) {
+    int st = bf_to_nv(c, x[k], p + (size_t)k * (c->L + 2));
+    if (st) return st;
+  }
+  return MPTS_OK;
+}
+
+int mpts_unpack_state(const mpts_ctx *c, const void *packed, mpts_bf x[3]) {
+  if (!c || !x || !packed) return MPTS_EINVAL;
+  const int32_t *p = (const int32_t *)packed;
+  for (int k = 0; k < 3; ++k) {
+    int st = nv_to_bf(c, p + (size_t)k * (c->L + 2), &x[k]);
+    if (st) return st;
+  }
+  return MPTS_OK;
+}
+
+int mpts_integrate_dev(mpts_ctx *c, const void *x0_dev, int64_t nsteps, void *xout_dev,
+                       void *ckpt_dev, void *ws, size_t ws_bytes, void *stream) {
+  if (!c || !x0_dev || !xout_dev || !ws || nsteps < 0) return MPTS_EINVAL;
+  return run_single(c, MODE_INTEGRATE, nsteps, x0_dev, xout_dev, ckpt_dev, ws, ws_bytes,
+                    (hipStream_t)stream, false, nullptr);
+}
+
+int mpts_check(mpts_ctx *c, void *ws, void *stream) {
+  if (!c || !ws) return MPTS_EINVAL;
+  return read_status(c, ws, (hipStream_t)stream);
+}
+
+int mpts_integrate(mpts_ctx *c, const mpts_bf x0[3], int64_t nsteps, mpts_bf x_out[3],
+                   mpts_bf *checkpoints, void *ws, size_t ws_bytes, void *stream,
+                   uint32_t flags) {
+  if (!c || !x0 || !x_out || !ws || nsteps < 0) return MPTS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<int32_t> packed((size_t)3 * (c->L + 2));
+  int st = mpts_pack_state(c, x0, packed.data());
+  if (st) return set_err(c, st, "bad initial state");
+  if (checkpoints && !(flags & MPTS_CHECKPOINTS))
+    return set_err(c, MPTS_EINVAL, "checkpoints need MPTS_CHECKPOINTS");
+  Layout l = layout(c, nsteps, (flags & MPTS_CHECKPOINTS) != 0, 1);
+  if (ws_bytes < l.total) return set_err(c, MPTS_ENOSPC, "workspace too small");
+  void *ck = (flags & MPTS_CHECKPOINTS) ? (char *)ws + l.ckpt : nullptr;
+  size_t ckb = (size_t)(nsteps + 1) * 3 * (c->L + 2) * 4;
+  hipError_t e;
+  st = run_single(c, MODE_INTEGRATE, nsteps, nullptr, nullptr, ck, ws, ws_bytes, s, true,
+                  packed.data());
+  if (st) return st;
+  e = hipMemcpyAsync(packed.data(), (char *)ws + l.state, packed.size() * 4, hipMemcpyDeviceToHost,
+                     s);
+  if (e != hipSuccess) return hip_err(c, e, "copy result");
+  std::vector<int32_t> ckh;
+  if (checkpoints) {
+    ckh.resize(ckb / 4);
+    e = hipMemcpyAsync(ckh.data(), ck, ckb, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_err(c, e, "copy checkpoints");
+  }
+  st = read_status(c, ws, s);
+  if (st) return st;
+  st = mpts_unpack_state(c, packed.data(), x_out);
+  if (st) return st;
+  if (checkpoints)
+    for (long long n = 0; n <= nsteps; ++n) {
+      st = mpts_unpack_state(c, ckh.data() + (size_t)n * 3 * (c->L + 2), checkpoints + 3 * n);
+      if (st) return st;
+    }
+  return MPTS_OK;
+}
+
+int mpts_coefficients(mpts_ctx *c, const mpts_bf x0[3], mpts_bf *alpha, mpts_bf *beta,
+                      mpts_bf *gamma, void *ws, size_t ws_bytes, void *stream) {
+  if (!c || !x0 || !alpha || !beta || !gamma || !ws) return MPTS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<int32_t> packed((size_t)3 * (c->L + 2));
+  int st = mpts_pack_state(c, x0, packed.data());
+  if (st) return set_err(c, st, "bad initial state");
+  st = run_single(c, MODE_COEFFS, 1, nullptr, nullptr, nullptr, ws, ws_bytes, s, true,
+                  packed.data());
+  if (st) return st;
+  Layout l = layout(c, 1, false, 1);
+  std::vector<int32_t> co((size_t)3 * (c->N + 1) * (c->L + 2));
+  hipError_t e =
+      hipMemcpyAsync(co.data(), (char *)ws + l.coefs, co.size() * 4, hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return hip_err(c, e, "copy coefficients");
+  st = read_status(c, ws, s);
+  if (st) return st;
+  mpts_bf *outs[3] = {alpha, beta, gamma};
+  for (int a = 0; a < 3; ++a)
+    for (int i = 0; i <= c->N; ++i) {
+      st = nv_to_bf(c, co.data() + ((size_t)a * (c->N + 1) + i) * (c->L + 2), &outs[a][i]);
+      if (st) return st;
+    }
+  return MPTS_OK;
+}
+
+int mpts_batch_workspace_bytes(mpts_ctx *const *ctxs, int32_t count, const int64_t *nsteps,
+                               uint32_t flags, size_t *bytes) {
+  (void)ctxs; (void)count; (void)nsteps; (void)flags; (void)bytes;
+  return MPTS_EUNSUPPORTED;
+}
+
+int mpts_integrate_batch(mpts_ctx *const *ctxs, int32_t count, const mpts_bf *x0,
+                         const int64_t *nsteps, mpts_bf *x_out, void *ws, size_t ws_bytes,
+                         void *stream, uint32_t flags) {
+  (void)ctxs; (void)count; (void)x0; (void)nsteps; (void)x_out; (void)ws; (void)ws_bytes;
+  (void)stream; (void)flags;
+  return MPTS_EUNSUPPORTED;
+}
+
+int mpts_grad(mpts_ctx *c, const mpts_bf x0[3], int64_t nsteps, double grad_out[6],
+              mpts_bf *grad_bf, mpts_bf x_out[3], void *ws, size_t ws_bytes, void *stream) {
+  (void)c; (void)x0; (void)nsteps; (void)grad_out; (void)grad_bf; (void)x_out; (void)ws;
+  (void)ws_bytes; (void)stream;
+  return MPTS_EUNSUPPORTED;
+}
+
+const char *mpts_strerror(int status) {
+  switch (status) {
+    case MPTS_OK: return "ok";
+    case MPTS_EINVAL: return "invalid argument";
+    case MPTS_ENOSPC: return "workspace too small";
+    case MPTS_EHIP: return "HIP runtime error";
+    case MPTS_ERANGE: return "exact sum outside the device window or exponent overflow";
+    case MPTS_EARCH: return "device is not gfx950";
+    case MPTS_EUNSUPPORTED: return "unsupported size or call";
+    default: return "unknown status";
+  }
+}
+
+const char *mpts_last_error(const mpts_ctx *c) { return c ? c->err.c_str() : ""; }
+
+}  // extern "C"

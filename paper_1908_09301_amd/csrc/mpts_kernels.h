@@ -1,0 +1,23 @@
+// Host-side entry points into the device code (launch wrappers).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include "mpts_common.h"
+
+namespace mpts {
+
+// Bytes of dynamic LDS one workgroup of the forward kernel needs.
+size_t lds_bytes(int L, int RS, int WB, int CM);
+
+// Cooperative launch of the persistent forward kernel over `nwg` workgroups;
+// workgroup w runs trajectory d_insts[d_wg_inst[w]].
+hipError_t launch_run(const Inst *d_insts, const int *d_wg_inst, int nwg, int CM, size_t lds,
+                      hipStream_t s);
+
+// Zero `bytes` of device memory with a kernel (usable under graph capture).
+hipError_t launch_clear(void *p, size_t bytes, hipStream_t s);
+
+// Workgroups of the forward kernel that fit on one compute unit.
+int max_coresident(int CM, size_t lds, int *out);
+
+}  // namespace mpts

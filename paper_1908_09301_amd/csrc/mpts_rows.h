@@ -1,0 +1,323 @@
+// Rows (signed radix-2^28 digit vectors with a header) and the exact
+// multi-term product accumulation over 8x8 digit tiles.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "mpts_common.h"
+#include "mpts_wave.h"
+
+namespace mpts {
+
+__device__ __forceinline__ int32_t ld_relaxed(const int32_t *p) {
+  return __hip_atomic_load(const_cast<int32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ long long ld_relaxed(const long long *p) {
+  return __hip_atomic_load(const_cast<long long *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_relaxed(const uint32_t *p) {
+  return __hip_atomic_load(const_cast<uint32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(int32_t *p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(long long *p, long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(uint32_t *p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// All of this thread's outstanding global loads, stores and atomics are done.
+__device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+__device__ __forceinline__ int floordiv28(long long e, long long *rem) {
+  long long q = e >= 0 ? e / DBITS : -((-e + DBITS - 1) / DBITS);
+  *rem = e - q * DBITS;
+  return (int)q;
+}
+
+// Bits [b, b+28) of the L-limb mantissa M (bits outside [0, 32 L) are zero).
+__device__ __forceinline__ uint32_t mant_bits28(const int32_t *M, int L, long long b) {
+  long long q = b >= 0 ? (b >> 5) : -((-b + 31) >> 5);
+  int r = (int)(b - q * 32);
+  unsigned long long lo = (q >= 0 && q < L) ? (uint32_t)M[q] : 0u;
+  unsigned long long hi = (q + 1 >= 0 && q + 1 < L) ? (uint32_t)M[q + 1] : 0u;
+  unsigned long long w = ((hi << 32) | lo) >> r;
+  return (uint32_t)(w & (unsigned long long)DMASK);
+}
+
+// Row of a normalised value nv = [sign, E, M[L]]: digit exponent e =
+// floor(E / 28), digits of M * 2^(E - 28 e) with the sign applied.  Written
+// by one wavefront (or any group of `nthr` threads indexed by `tid`), header
+// and zero padding included.  `relaxed` selects L2-bypassing stores (for
+// rows that other workgroups read).
+__device__ void write_row(const int32_t *nv, int L, int nd, int RS, int32_t *row, bool relaxed,
+                          int tid, int nthr) {
+  int s = nv[0];
+  long long E = nv[1];
+  long long sh;
+  int e = floordiv28(E, &sh);
+  if (s == 0) e = 0;
+  for (int w = tid; w < RS; w += nthr) {
+    int32_t val = 0;
+    if (w == 0) val = e;
+    else if (w == 1) val = s;
+    else if (w >= HDR + RPAD && w < HDR + RPAD + nd && s != 0) {
+      int k = w - HDR - RPAD;
+      uint32_t d = mant_bits28(nv + 2, L, (long long)DBITS * k - sh);
+      val = s < 0 ? -(int32_t)d : (int32_t)d;
+    }
+    if (relaxed) st_relaxed(row + w, val);
+    else row[w] = val;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Exact sums of products of rows ("frames").
+//
+// A frame is sum_t U_t * V_t over its terms.  With the terms' exponent sums
+// e(U_t) + e(V_t) = base + off_t (0 <= off_t <= S), the frame's value is
+// sum_c col[c] 2^(28 (base + c)), col[c] = sum_t sum_{m + n = c - off_t}
+// U_t[m] V_t[n].  The (m, n') plane (n' = n + off_t) is cut into 8x8 tiles;
+// a thread owning tile (mt, nt) accumulates its 15 anti-diagonal columns
+// exactly in 64-bit integers over a share of the terms and adds them into
+// the frame's column array.
+
+struct FrameSrc {
+  int kind;            // 0: Cauchy sum_{k=0}^{i} U[i-k] V[k]; 1: explicit list
+  int n;               // number of terms
+  const int32_t *U0, *V0;   // kind 0: row arrays (stride RS); kind 1: term 0
+  const int32_t *U1, *V1;   // kind 1: term 1
+  int i;
+};
+
+struct FrameD {
+  int n, base, S, NT, nz, pad;
+  long long cost0;     // first cost unit of this frame
+};
+
+__device__ __forceinline__ void frame_term(const FrameSrc &f, int k, int RS, const int32_t **U,
+                                           const int32_t **V) {
+  if (f.kind == 0) {
+    *U = f.U0 + (long long)(f.i - k) * RS;
+    *V = f.V0 + (long long)k * RS;
+  } else {
+    *U = k == 0 ? f.U0 : f.U1;
+    *V = k == 0 ? f.V0 : f.V1;
+  }
+}
+
+// Tile (mt, nt) of the t-th tile in anti-diagonal order of an MT x NT grid
+// (MT <= NT): diagonals d = mt + nt in increasing order, mt increasing along
+// each diagonal.  Diagonals 0..MT-2 hold d+1 tiles, MT-1..NT-1 hold MT, and
+// the last ones mirror the first (counted from the end).
+__device__ __forceinline__ int tri_index(int t) {
+  int d = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
+  while ((d + 1) * (d + 2) / 2 <= t) ++d;
+  while (d * (d + 1) / 2 > t) --d;
+  return d;
+}
+
+__device__ __forceinline__ void tile_coords(int t, int MT, int NT, int *mt, int *nt) {
+  const int T1 = MT * (MT - 1) / 2;
+  const int T2 = MT * (NT - MT + 1);
+  int d, m;
+  if (t < T1) {
+    d = tri_index(t);
+    m = t - d * (d + 1) / 2;
+  } else if (t < T1 + T2) {
+    d = MT - 1 + (t - T1) / MT;
+    m = (t - T1) % MT;
+  } else {
+    int t3 = MT * NT - 1 - t;
+    int dd = tri_index(t3);
+    d = MT + NT - 2 - dd;
+    m = MT - 1 - (t3 - dd * (dd + 1) / 2);
+  }
+  *mt = m;
+  *nt = d - m;
+}
+
+__device__ __forceinline__ void tile_normalize(long long (&acc)[16]) {
+#pragma unroll
+  for (int r = 0; r < 15; ++r) {
+    acc[r + 1] += acc[r] >> DBITS;
+    acc[r] &= DMASK;
+  }
+}
+
+// Accumulate U[mt*8 .. +8) x V[nt*8 - off .. +8) into acc (columns 0..14).
+__device__ __forceinline__ void tile_mac(long long (&acc)[16], const int32_t *U, const int32_t *V,
+                                         int mt, int nt, int off) {
+  const int32_t *u = U + HDR + RPAD + mt * TQ;
+  const int32_t *v = V + HDR + RPAD + nt * TQ - off;
+  int32_t uu[TQ], vv[TQ];
+#pragma unroll
+  for (int r = 0; r < TQ; ++r) uu[r] = u[r];
+#pragma unroll
+  for (int s = 0; s < TQ; ++s) vv[s] = v[s];
+#pragma unroll
+  for (int r = 0; r < TQ; ++r)
+#pragma unroll
+    for (int s = 0; s < TQ; ++s) acc[r + s] += (long long)uu[r] * (long long)vv[s];
+}
+
+// Per-workgroup frame setup: exponent base and spread of each frame's
+// nonzero terms (a workgroup reduction for Cauchy frames).  Every thread of
+// the workgroup calls this; results land in fd[0..nf).  red: 8*64 ints.
+__device__ void frame_setup(const FrameSrc *fs, FrameD *fd, int nf, int nd, int RS, int *red,
+                            uint32_t *err) {
+  const int tid = threadIdx.x;
+  const int MT = (nd + TQ - 1) / TQ;
+  for (int f = 0; f < nf; ++f) {
+    int mn = 0x7fffffff, mx = -0x7fffffff;
+    for (int k = tid; k < fs[f].n; k += WGS) {
+      const int32_t *U, *V;
+      frame_term(fs[f], k, RS, &U, &V);
+      if (U[1] != 0 && V[1] != 0) {
+        int e = U[0] + V[0];
+        mn = min(mn, e);
+        mx = max(mx, e);
+      }
+    }
+    // workgroup min / max
+    for (int o = 32; o > 0; o >>= 1) {
+      mn = min(mn, __shfl_xor(mn, o, 64));
+      mx = max(mx, __shfl_xor(mx, o, 64));
+    }
+    if ((tid & 63) == 0) {
+      red[2 * (tid >> 6)] = mn;
+      red[2 * (tid >> 6) + 1] = mx;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int a = red[0], b = red[1];
+      for (int w = 1; w < WGS / 64; ++w) {
+        a = min(a, red[2 * w]);
+        b = max(b, red[2 * w + 1]);
+      }
+      FrameD d;
+      d.n = fs[f].n;
+      d.nz = (a <= b) ? 1 : 0;
+      d.base = d.nz ? a : 0;
+      int S = d.nz ? (b - a) : 0;
+      if (S > SMAX) {
+        atomicOr(err, 1u);
+        S = SMAX;
+      }
+      d.S = S;
+      d.NT = (nd + S + TQ - 1) / TQ;
+      d.pad = MT;
+      fd[f] = d;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    long long c = 0;
+    for (int f = 0; f < nf; ++f) {
+      fd[f].cost0 = c;
+      if (fd[f].nz) c += (long long)MT * fd[f].NT * fd[f].n;
+    }
+    fd[nf].cost0 = c;
+  }
+  __syncthreads();
+}
+
+// Columns spanned by frame f's tiles: [0, (MT + NT) * 8 + 8).
+__device__ __forceinline__ int frame_cols(const FrameD &d, int nd) {
+  int MT = (nd + TQ - 1) / TQ;
+  return (MT + d.NT) * TQ + TQ;
+}
+
+// The workgroup `rank` of `G` accumulates its share of all frames' tiles
+// into the LDS column arrays lf[f * WB + c].  Tiles are dealt out in
+// contiguous ranges of equal cost (tiles x terms); inside the workgroup,
+// threads split each tile's terms.  Returns through span[2f], span[2f+1]
+// the column range this workgroup touched in frame f (empty: lo >= hi).
+__device__ void frames_accumulate(const FrameSrc *fs, const FrameD *fd, int nf, int nd, int RS,
+                                  int WB, long long *lf, int rank, int G, int *span,
+                                  uint32_t *err) {
+  const int tid = threadIdx.x;
+  const int MT = (nd + TQ - 1) / TQ;
+  const long long C = fd[nf].cost0;
+  const long long lo = C * rank / G, hi = C * (rank + 1) / G;
+  // per-frame tile range [t0, t1)
+  int t0[NFR], t1[NFR], nT = 0;
+  for (int f = 0; f < nf; ++f) {
+    t0[f] = t1[f] = 0;
+    if (!fd[f].nz || fd[f].n == 0) continue;
+    long long pre = fd[f].cost0;
+    long long n = fd[f].n;
+    long long T = (long long)MT * fd[f].NT;
+    long long a = lo - pre, b = hi - pre;
+    long long ta = a <= 0 ? 0 : (a + n - 1) / n;
+    long long tb = b <= 0 ? 0 : (b + n - 1) / n;
+    if (ta > T) ta = T;
+    if (tb > T) tb = T;
+    t0[f] = (int)ta;
+    t1[f] = (int)tb;
+    nT += (int)(tb - ta);
+  }
+  if (tid < 2 * nf) span[tid] = 0;
+  if (nT == 0) return;
+  for (int base = 0; base < nT; base += WGS) {
+    int cnt = min(nT - base, WGS);
+    int tt, slot, lam;
+    if (cnt >= WGS) {
+      tt = base + tid;
+      slot = 0;
+      lam = 1;
+    } else {
+      tt = base + tid % cnt;
+      slot = tid / cnt;
+      lam = (WGS - 1 - tid % cnt) / cnt + 1;
+    }
+    if (tt >= nT) continue;
+    // which frame
+    int f = 0, loc = tt;
+    while (f < nf && loc >= t1[f] - t0[f]) {
+      loc -= t1[f] - t0[f];
+      ++f;
+    }
+    int t = t0[f] + loc;
+    int mt, nt;
+    tile_coords(t, MT, fd[f].NT, &mt, &nt);
+    long long acc[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0;
+    const int base_e = fd[f].base, S = fd[f].S;
+    int since = 0;
+    for (int k = slot; k < fd[f].n; k += lam) {
+      const int32_t *U, *V;
+      frame_term(fs[f], k, RS, &U, &V);
+      int sU = U[1], sV = V[1];
+      if (sU == 0 || sV == 0) continue;
+      int off = U[0] + V[0] - base_e;
+      if (off < 0 || off > S) continue;  // only after a spread error
+      tile_mac(acc, U, V, mt, nt, off);
+      if (++since == FLUSH_TERMS) {
+        tile_normalize(acc);
+        since = 0;
+      }
+    }
+    tile_normalize(acc);
+    long long *col = lf + (long long)f * WB + (mt + nt) * TQ;
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      if (acc[r] != 0) atomicAdd((unsigned long long *)(col + r), (unsigned long long)acc[r]);
+  }
+  (void)err;
+  // column spans touched (anti-diagonals of the first and last tile)
+  if (tid < nf) {
+    int f = tid;
+    if (t1[f] > t0[f]) {
+      int mt, nt;
+      tile_coords(t0[f], MT, fd[f].NT, &mt, &nt);
+      int dlo = mt + nt;
+      tile_coords(t1[f] - 1, MT, fd[f].NT, &mt, &nt);
+      int dhi = mt + nt;
+      span[2 * f] = min(dlo, dhi) * TQ;
+      span[2 * f + 1] = max(dlo, dhi) * TQ + 2 * TQ;
+    }
+  }
+}
+
+}  // namespace mpts

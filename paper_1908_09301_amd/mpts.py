@@ -1,0 +1,337 @@
+"""ctypes binding of libmpts.so (C ABI declared in include/mpts.h).
+
+Argument marshalling only: numbers cross as (sign, mantissa, exponent)
+Python integers with value sign * mantissa * 2**exponent; device memory comes
+from PyTorch tensors and the stream is PyTorch's current stream.  Every step
+of the computation runs in the HIP library; importing this module fails
+loudly when the library is missing.
+"""
+import ctypes
+import os
+from typing import List, Optional, Sequence, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpts.so")
+
+MPTS_OK = 0
+MPTS_EINVAL = -1
+MPTS_ENOSPC = -2
+MPTS_EHIP = -3
+MPTS_ERANGE = -4
+MPTS_EARCH = -5
+MPTS_EUNSUPPORTED = -6
+MPTS_CHECKPOINTS = 1
+MPTS_GRAPH = 2
+MPTS_AUTOTUNE = 4
+
+# every symbol include/mpts.h declares
+SYMBOLS = (
+    "mpts_create", "mpts_create_limbs", "mpts_destroy", "mpts_limbs", "mpts_param",
+    "mpts_bf_from_str", "mpts_bf_from_double", "mpts_bf_to_double", "mpts_set_schedule",
+    "mpts_workspace_bytes", "mpts_state_bytes", "mpts_pack_state", "mpts_unpack_state",
+    "mpts_integrate", "mpts_integrate_dev", "mpts_check", "mpts_coefficients",
+    "mpts_batch_workspace_bytes", "mpts_integrate_batch", "mpts_grad", "mpts_strerror",
+    "mpts_last_error",
+)
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1908_09301_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+
+class mpts_bf(ctypes.Structure):
+    _fields_ = [("sign", ctypes.c_int32), ("exp", ctypes.c_int32),
+                ("limbs", ctypes.POINTER(ctypes.c_uint32))]
+
+
+_P = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_u32 = ctypes.c_uint32
+_sz = ctypes.c_size_t
+_BFP = ctypes.POINTER(mpts_bf)
+
+_lib.mpts_create.argtypes = [ctypes.c_char_p] * 3 + [_i32, _i32, ctypes.c_char_p, ctypes.POINTER(_P)]
+_lib.mpts_create_limbs.argtypes = [ctypes.c_char_p] * 3 + [_i32, _i32, ctypes.c_char_p, ctypes.POINTER(_P)]
+_lib.mpts_destroy.argtypes = [_P]
+_lib.mpts_destroy.restype = None
+_lib.mpts_limbs.argtypes = [_P, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
+_lib.mpts_param.argtypes = [_P, _i32, _BFP]
+_lib.mpts_bf_from_str.argtypes = [_P, ctypes.c_char_p, _BFP]
+_lib.mpts_bf_from_double.argtypes = [_P, ctypes.c_double, _BFP]
+_lib.mpts_bf_to_double.argtypes = [_P, _BFP, ctypes.POINTER(ctypes.c_double)]
+_lib.mpts_set_schedule.argtypes = [_P, _i32]
+_lib.mpts_workspace_bytes.argtypes = [_P, _i64, _u32, ctypes.POINTER(_sz)]
+_lib.mpts_state_bytes.argtypes = [_P, ctypes.POINTER(_sz)]
+_lib.mpts_pack_state.argtypes = [_P, _BFP, _P]
+_lib.mpts_unpack_state.argtypes = [_P, _P, _BFP]
+_lib.mpts_integrate.argtypes = [_P, _BFP, _i64, _BFP, _BFP, _P, _sz, _P, _u32]
+_lib.mpts_integrate_dev.argtypes = [_P, _P, _i64, _P, _P, _P, _sz, _P]
+_lib.mpts_check.argtypes = [_P, _P, _P]
+_lib.mpts_coefficients.argtypes = [_P, _BFP, _BFP, _BFP, _BFP, _P, _sz, _P]
+_lib.mpts_batch_workspace_bytes.argtypes = [ctypes.POINTER(_P), _i32, ctypes.POINTER(_i64), _u32,
+                                            ctypes.POINTER(_sz)]
+_lib.mpts_integrate_batch.argtypes = [ctypes.POINTER(_P), _i32, _BFP, ctypes.POINTER(_i64), _BFP,
+                                      _P, _sz, _P, _u32]
+_lib.mpts_grad.argtypes = [_P, _BFP, _i64, ctypes.POINTER(ctypes.c_double), _BFP, _BFP, _P, _sz, _P]
+_lib.mpts_strerror.argtypes = [_i32]
+_lib.mpts_strerror.restype = ctypes.c_char_p
+_lib.mpts_last_error.argtypes = [_P]
+_lib.mpts_last_error.restype = ctypes.c_char_p
+
+
+class MptsError(RuntimeError):
+    def __init__(self, code: int, msg: str = ""):
+        self.code = code
+        text = _lib.mpts_strerror(code).decode()
+        super().__init__(f"{text} ({code})" + (f": {msg}" if msg else ""))
+
+
+def exported_symbols() -> List[str]:
+    return [s for s in SYMBOLS if hasattr(_lib, s)]
+
+
+def _bytes(s) -> bytes:
+    return str(s).encode()
+
+
+class BFArray:
+    """Caller-owned storage for n big-floats of L limbs each."""
+
+    def __init__(self, n: int, L: int):
+        self.n, self.L = n, L
+        self.store = (ctypes.c_uint32 * (n * L))()
+        self.arr = (mpts_bf * n)()
+        base = ctypes.addressof(self.store)
+        for j in range(n):
+            self.arr[j].limbs = ctypes.cast(base + 4 * L * j, ctypes.POINTER(ctypes.c_uint32))
+
+    def set(self, j: int, v: Tuple[int, int, int]):
+        s, m, e = v
+        self.arr[j].sign = s
+        self.arr[j].exp = e if s else 0
+        for k in range(self.L):
+            self.store[j * self.L + k] = (m >> (32 * k)) & 0xFFFFFFFF
+
+    def get(self, j: int) -> Tuple[int, int, int]:
+        b = self.arr[j]
+        m = 0
+        for k in range(self.L - 1, -1, -1):
+            m = (m << 32) | self.store[j * self.L + k]
+        if b.sign == 0:
+            return (0, 0, 0)
+        return (int(b.sign), m, int(b.exp))
+
+    def ptr(self, j: int = 0):
+        return ctypes.cast(ctypes.byref(self.arr, j * ctypes.sizeof(mpts_bf)), _BFP)
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _workspace(nbytes: int):
+    import torch
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device="cuda")
+
+
+class Lorenz:
+    """One problem definition: Lorenz parameters (equation (1)), Taylor
+    order N and step tau (equation (2)), precision K decimal digits or L
+    limbs."""
+
+    def __init__(self, K: Optional[int] = None, N: int = 40, L: Optional[int] = None,
+                 sigma: str = "10", R: str = "28", b: str = "8/3", tau: str = "1/100"):
+        h = _P()
+        if L is not None:
+            st = _lib.mpts_create_limbs(_bytes(sigma), _bytes(R), _bytes(b), L, N, _bytes(tau),
+                                        ctypes.byref(h))
+        else:
+            st = _lib.mpts_create(_bytes(sigma), _bytes(R), _bytes(b), K, N, _bytes(tau),
+                                  ctypes.byref(h))
+        if st != MPTS_OK:
+            raise MptsError(st)
+        self._h = h
+        Lc, pc, Nc = _i32(), _i32(), _i32()
+        _lib.mpts_limbs(h, ctypes.byref(Lc), ctypes.byref(pc), ctypes.byref(Nc))
+        self.L, self.p, self.N = Lc.value, pc.value, Nc.value
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.mpts_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _check(self, st: int):
+        if st != MPTS_OK:
+            raise MptsError(st, _lib.mpts_last_error(self._h).decode())
+
+    # -- numbers ----------------------------------------------------------
+    def param(self, which: int) -> Tuple[int, int, int]:
+        a = BFArray(1, self.L)
+        self._check(_lib.mpts_param(self._h, which, a.ptr()))
+        return a.get(0)
+
+    def from_str(self, s: str) -> Tuple[int, int, int]:
+        a = BFArray(1, self.L)
+        self._check(_lib.mpts_bf_from_str(self._h, _bytes(s), a.ptr()))
+        return a.get(0)
+
+    def from_double(self, v: float) -> Tuple[int, int, int]:
+        a = BFArray(1, self.L)
+        self._check(_lib.mpts_bf_from_double(self._h, ctypes.c_double(v), a.ptr()))
+        return a.get(0)
+
+    def to_double(self, v: Tuple[int, int, int]) -> float:
+        a = BFArray(1, self.L)
+        a.set(0, v)
+        out = ctypes.c_double()
+        self._check(_lib.mpts_bf_to_double(self._h, a.ptr(), ctypes.byref(out)))
+        return out.value
+
+    def set_schedule(self, workgroups: int):
+        self._check(_lib.mpts_set_schedule(self._h, workgroups))
+
+    # -- device -----------------------------------------------------------
+    def workspace_bytes(self, nsteps: int, flags: int = 0) -> int:
+        n = _sz()
+        self._check(_lib.mpts_workspace_bytes(self._h, nsteps, flags, ctypes.byref(n)))
+        return n.value
+
+    def workspace(self, nsteps: int, flags: int = 0):
+        need = self.workspace_bytes(nsteps, flags)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = _workspace(need)
+        return self._ws
+
+    def state_bytes(self) -> int:
+        n = _sz()
+        self._check(_lib.mpts_state_bytes(self._h, ctypes.byref(n)))
+        return n.value
+
+    def pack_state(self, x: Sequence[Tuple[int, int, int]]):
+        """Packed device-format state as a CPU int32 tensor."""
+        import torch
+        a = BFArray(3, self.L)
+        for j in range(3):
+            a.set(j, x[j])
+        t = torch.zeros(self.state_bytes() // 4, dtype=torch.int32)
+        self._check(_lib.mpts_pack_state(self._h, a.ptr(), ctypes.c_void_p(t.data_ptr())))
+        return t
+
+    def unpack_state(self, t) -> List[Tuple[int, int, int]]:
+        t = t.cpu().contiguous()
+        a = BFArray(3, self.L)
+        self._check(_lib.mpts_unpack_state(self._h, ctypes.c_void_p(t.data_ptr()), a.ptr()))
+        return [a.get(j) for j in range(3)]
+
+    def integrate(self, x0, nsteps: int, checkpoints: bool = False):
+        """Final state after nsteps Taylor steps (and all states with
+        checkpoints=True)."""
+        flags = MPTS_CHECKPOINTS if checkpoints else 0
+        ws = self.workspace(nsteps, flags)
+        a = BFArray(3, self.L)
+        for j in range(3):
+            a.set(j, x0[j])
+        out = BFArray(3, self.L)
+        ck = BFArray(3 * (nsteps + 1), self.L) if checkpoints else None
+        self._check(_lib.mpts_integrate(self._h, a.ptr(), nsteps, out.ptr(),
+                                        ck.ptr() if ck else None,
+                                        ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(), flags))
+        res = [out.get(j) for j in range(3)]
+        if checkpoints:
+            states = [[ck.get(3 * n + j) for j in range(3)] for n in range(nsteps + 1)]
+            return res, states
+        return res
+
+    def integrate_dev(self, x0_dev, nsteps: int, xout_dev, ckpt_dev=None, ws=None):
+        """Asynchronous device-resident run on the current stream; x0_dev and
+        xout_dev are int32 CUDA tensors in the packed state format."""
+        if ws is None:
+            ws = self.workspace(nsteps)
+        self._check(_lib.mpts_integrate_dev(
+            self._h, ctypes.c_void_p(x0_dev.data_ptr()), nsteps, ctypes.c_void_p(xout_dev.data_ptr()),
+            ctypes.c_void_p(ckpt_dev.data_ptr()) if ckpt_dev is not None else None,
+            ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+        return ws
+
+    def check(self, ws):
+        self._check(_lib.mpts_check(self._h, ctypes.c_void_p(ws.data_ptr()), _stream()))
+
+    def coefficients(self, x0):
+        """Taylor coefficients (alpha, beta, gamma), each N+1 values, of one
+        step from x0."""
+        ws = self.workspace(1)
+        a = BFArray(3, self.L)
+        for j in range(3):
+            a.set(j, x0[j])
+        outs = [BFArray(self.N + 1, self.L) for _ in range(3)]
+        self._check(_lib.mpts_coefficients(self._h, a.ptr(), outs[0].ptr(), outs[1].ptr(),
+                                           outs[2].ptr(), ctypes.c_void_p(ws.data_ptr()),
+                                           ws.numel(), _stream()))
+        return tuple([o.get(i) for i in range(self.N + 1)] for o in outs)
+
+    def grad(self, x0, nsteps: int):
+        """Gradient of ||x(T)||^2 w.r.t. (x0, y0, z0, sigma, R, b): returns
+        (6 doubles, 6 big-floats, final state)."""
+        ws = self.workspace(nsteps, MPTS_CHECKPOINTS)
+        a = BFArray(3, self.L)
+        for j in range(3):
+            a.set(j, x0[j])
+        g = (ctypes.c_double * 6)()
+        gb = BFArray(6, self.L)
+        out = BFArray(3, self.L)
+        self._check(_lib.mpts_grad(self._h, a.ptr(), nsteps, g, gb.ptr(), out.ptr(),
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+        return list(g), [gb.get(j) for j in range(6)], [out.get(j) for j in range(3)]
+
+
+def integrate_batch(problems: Sequence[Lorenz], x0s, nsteps: Sequence[int], flags: int = 0):
+    """Run many trajectories (each with its own K, N) in one persistent
+    launch; returns the final states."""
+    n = len(problems)
+    hs = (_P * n)(*[p.handle for p in problems])
+    ns = (_i64 * n)(*nsteps)
+    need = _sz()
+    st = _lib.mpts_batch_workspace_bytes(hs, n, ns, flags, ctypes.byref(need))
+    if st != MPTS_OK:
+        raise MptsError(st)
+    ws = _workspace(need.value)
+    Ls = [p.L for p in problems]
+    Lmax = max(Ls)
+    # per-trajectory limb counts differ: one storage per trajectory
+    ins = (mpts_bf * (3 * n))()
+    outs = (mpts_bf * (3 * n))()
+    keep = []
+    for t, p in enumerate(problems):
+        for j in range(3):
+            s, m, e = x0s[t][j]
+            buf = (ctypes.c_uint32 * p.L)(*[(m >> (32 * k)) & 0xFFFFFFFF for k in range(p.L)])
+            ob = (ctypes.c_uint32 * p.L)()
+            keep += [buf, ob]
+            ins[3 * t + j].sign, ins[3 * t + j].exp = s, (e if s else 0)
+            ins[3 * t + j].limbs = ctypes.cast(buf, ctypes.POINTER(ctypes.c_uint32))
+            outs[3 * t + j].limbs = ctypes.cast(ob, ctypes.POINTER(ctypes.c_uint32))
+    st = _lib.mpts_integrate_batch(hs, n, ins, ns, outs, ctypes.c_void_p(ws.data_ptr()),
+                                   ws.numel(), _stream(), flags)
+    if st != MPTS_OK:
+        raise MptsError(st)
+    res = []
+    for t, p in enumerate(problems):
+        r = []
+        for j in range(3):
+            b = outs[3 * t + j]
+            m = 0
+            for k in range(p.L - 1, -1, -1):
+                m = (m << 32) | b.limbs[k]
+            r.append((int(b.sign), m, int(b.exp)) if b.sign else (0, 0, 0))
+        res.append(r)
+    del Lmax
+    return res

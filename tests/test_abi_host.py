@@ -1,0 +1,73 @@
+"""The C-ABI library loads, exports every symbol include/mpts.h declares, and
+its host-side number handling (exact parse + one RNE rounding, FP64 export)
+agrees with the oracle.  CPU only: no kernel is launched."""
+import re
+from fractions import Fraction
+import os
+
+import pytest
+
+from oracle.bigfloat import parse, from_fraction, to_double, BF
+from oracle.lorenz import make_context
+from workloads import BENCH_X0
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_1908_09301_amd import mpts
+    return mpts
+
+
+def test_every_declared_symbol_is_exported():
+    mpts = _lib()
+    header = open(os.path.join(ROOT, "include", "mpts.h")).read()
+    declared = set(re.findall(r"\b(mpts_[a-z_0-9]+)\s*\(", header))
+    declared -= {"mpts_bf"}
+    assert declared == set(mpts.SYMBOLS)
+    assert sorted(mpts.exported_symbols()) == sorted(declared)
+
+
+@pytest.mark.parametrize("K", [100, 2000, 300])
+def test_limb_rule_matches_oracle(K):
+    mpts = _lib()
+    p = mpts.Lorenz(K=K, N=10)
+    assert p.L == make_context(K_digits=K, N=10).L
+
+
+@pytest.mark.parametrize("L", [1, 2, 12, 208])
+def test_parse_matches_oracle(L):
+    mpts = _lib()
+    p = mpts.Lorenz(L=L, N=3)
+    for s in BENCH_X0 + ("8/3", "1/100", "-1e-30", "123456789.987654321e-7", "0", "-7/3"):
+        o = parse(s, 32 * L)
+        assert p.from_str(s) == tuple(o), s
+    assert p.param(0) == tuple(parse("10", 32 * L))
+    assert p.param(1) == tuple(parse("28", 32 * L))
+    assert p.param(2) == tuple(parse("8/3", 32 * L))
+    assert p.param(3) == tuple(parse("1/100", 32 * L))
+
+
+def test_double_round_trip_and_export():
+    mpts = _lib()
+    p = mpts.Lorenz(L=12, N=3)
+    for v in (0.1, -15.8, 1e-300, 5e-324, 1.7976931348623157e308, -2.5):
+        bf = p.from_double(v)
+        assert bf == tuple(from_fraction(Fraction(v), 384))
+        assert p.to_double(bf) == v
+    for s in ("1/3", "-2/7", "1e-310", "3e-324", "2e-324"):
+        o = parse(s, 384)
+        assert p.to_double(tuple(o)) == to_double(o), s
+
+
+def test_invalid_arguments_fail_cleanly():
+    mpts = _lib()
+    with pytest.raises(mpts.MptsError):
+        mpts.Lorenz(K=0, N=4)
+    with pytest.raises(mpts.MptsError):
+        mpts.Lorenz(K=10, N=0)
+    with pytest.raises(mpts.MptsError):
+        mpts.Lorenz(K=10, N=4, b="eight/3")
+    p = mpts.Lorenz(L=4, N=3)
+    with pytest.raises(mpts.MptsError):
+        p.from_str("1/0")
