@@ -56,6 +56,11 @@ struct Inst {
   uint32_t *sync;     // SY_* words
   // adjoint
   int32_t *adj;       // adjoint scratch (MODE_ADJOINT)
+  unsigned long long *prof;  // per-phase wall-clock ticks (null: not recorded)
 };
+
+// phases timed when Inst::prof is set (leader slots 0..15, one follower 16..31)
+enum { PH_SETUP = 0, PH_ACCUM, PH_FLUSH, PH_WAIT, PH_FINAL, PH_CLEAR, PH_HORNER, PH_STEP0,
+       PH_NPHASE = 16 };
 
 }  // namespace mpts

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -308,7 +309,7 @@ int choose_cm(int nd) {
 }
 
 struct Layout {
-  size_t sync, cnorm, state, consts, rows, gframes, coefs, ckpt, inst, wgmap, total;
+  size_t prof, sync, cnorm, state, consts, rows, gframes, coefs, ckpt, inst, wgmap, total;
 };
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -318,6 +319,8 @@ constexpr int kMaxWG = 4096;
 Layout layout(const mpts_ctx *c, long long nsteps, bool ckpt, int nwg) {
   Layout l;
   size_t o = 0;
+  l.prof = o;
+  o = al(o + 2 * PH_NPHASE * 8);
   l.sync = o;
   o = al(o + SY_WORDS * 4);
   l.cnorm = o;
@@ -354,7 +357,7 @@ int check_device(mpts_ctx *c) {
   if (strncmp(pr.gcnArchName, "gfx950", 6) != 0)
     return set_err(c, MPTS_EARCH, std::string("device is ") + pr.gcnArchName + ", need gfx950");
   c->cus = pr.multiProcessorCount;
-  c->lds = lds_bytes(c->L, c->RS, c->WB, c->CM);
+  c->lds = lds_bytes(c->L, c->N, c->RS, c->WB, c->CM);
   if (max_coresident(c->CM, c->lds, &c->max_per_cu) != 0 || c->max_per_cu < 1)
     return set_err(c, MPTS_EUNSUPPORTED, "kernel does not fit one compute unit");
   return MPTS_OK;
@@ -438,6 +441,11 @@ int run_single(mpts_ctx *c, int mode, long long nsteps, const void *x0_dev, void
   if (ws_bytes < l.total) return set_err(c, MPTS_ENOSPC, "workspace too small");
   char *base = (char *)ws;
   hipError_t e;
+  const bool phases = getenv("MPTS_PHASES") != nullptr;
+  if (phases) {
+    e = launch_clear(base + l.prof, 2 * PH_NPHASE * 8, s);
+    if (e != hipSuccess) return hip_err(c, e, "clear");
+  }
   e = launch_clear(base + l.sync, SY_WORDS * 4, s);
   if (e != hipSuccess) return hip_err(c, e, "clear");
   e = launch_clear(base + l.gframes, (size_t)2 * NFR * c->WB * 8, s);
@@ -470,6 +478,7 @@ int run_single(mpts_ctx *c, int mode, long long nsteps, const void *x0_dev, void
   I.ckpt = (int32_t *)ckpt_dev;
   I.gframes = (long long *)(base + l.gframes);
   I.sync = (uint32_t *)(base + l.sync);
+  I.prof = phases ? (unsigned long long *)(base + l.prof) : nullptr;
   e = hipMemcpyAsync(base + l.inst, &I, sizeof(I), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_err(c, e, "copy descriptor");
   e = launch_clear(base + l.wgmap, (size_t)G * 4, s);
@@ -490,6 +499,24 @@ int read_status(mpts_ctx *c, void *ws, hipStream_t s) {
   if (e != hipSuccess) return hip_err(c, e, "read status");
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_err(c, e, "synchronize");
+  if (getenv("MPTS_PHASES")) {
+    unsigned long long ph[2 * PH_NPHASE];
+    if (hipMemcpy(ph, (char *)ws + l.prof, sizeof(ph), hipMemcpyDeviceToHost) == hipSuccess) {
+      int rate = 0;
+      int dev = 0;
+      (void)hipGetDevice(&dev);
+      (void)hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev);
+      double us = rate > 0 ? 1e3 / rate : 0.0;  // rate in kHz
+      static const char *nm[13] = {"setup", "accum", "flush", "wait", "final", "clear", "horner",
+                                   "step0", "f.res1", "f.round1", "f.res2", "f.div", "f.row"};
+      fprintf(stderr, "mpts phases (us):");
+      for (int w2 = 0; w2 < 2; ++w2) {
+        fprintf(stderr, w2 ? "\n  wg1:" : "\n  leader:");
+        for (int j = 0; j < (w2 ? 8 : 13); ++j) fprintf(stderr, " %s=%.1f", nm[j], ph[w2 * PH_NPHASE + j] * us);
+      }
+      fprintf(stderr, "\n");
+    }
+  }
   if (w & 4u) return set_err(c, MPTS_EHIP, "device synchronisation timed out");
   if (w & 3u) return set_err(c, MPTS_ERANGE, "exact sum outside the device window or exponent overflow");
   return MPTS_OK;

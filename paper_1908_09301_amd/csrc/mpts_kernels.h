@@ -7,7 +7,7 @@
 namespace mpts {
 
 // Bytes of dynamic LDS one workgroup of the forward kernel needs.
-size_t lds_bytes(int L, int RS, int WB, int CM);
+size_t lds_bytes(int L, int N, int RS, int WB, int CM);
 
 // Cooperative launch of the persistent forward kernel over `nwg` workgroups;
 // workgroup w runs trajectory d_insts[d_wg_inst[w]].

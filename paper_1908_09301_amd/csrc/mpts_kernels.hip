@@ -35,11 +35,12 @@ struct Addend {
 };
 
 // Exact sum of one product frame (columns from global memory or LDS) and up
-// to three addends, resolved into sign and magnitude digits in `cols`
-// (reinterpreted as int32 digits).  Single wavefront.
+// to three addends, resolved into sign and magnitude digits dig[0..64C).
+// Each lane gathers its own chunk of columns straight into registers.
+// Single wavefront.
 template <int CM>
 __device__ int combine_resolve(const long long *frame, bool frame_global, const FrameD *fd,
-                               int nd, int L, const Addend *adds, int nadd, long long *cols,
+                               int nd, int L, const Addend *adds, int nadd, int32_t *dig,
                                int *C, long long *dexp, uint32_t *err) {
   const int lane = lane_id();
   long long lo = (1LL << 40), hi = -(1LL << 40);
@@ -49,18 +50,18 @@ __device__ int combine_resolve(const long long *frame, bool frame_global, const 
     lo = fd->base;
     hi = (long long)fd->base + fcols;
   }
-  long long ae[3];
+  long long ae[3], ash[3];
   int as[3];
   for (int a = 0; a < nadd; ++a) {
     long long e;
     int s;
+    ash[a] = 0;
     if (adds[a].is_row) {
       e = adds[a].p[0];
       s = adds[a].p[1];
     } else {
-      long long sh;
       s = adds[a].p[0];
-      e = floordiv28(adds[a].p[1], &sh);
+      e = floordiv28(adds[a].p[1], &ash[a]);
     }
     ae[a] = e;
     as[a] = s;
@@ -69,51 +70,66 @@ __device__ int combine_resolve(const long long *frame, bool frame_global, const 
       hi = max(hi, e + nd);
     }
   }
-  if (lo > hi) {  // everything zero
+  if (lo > hi || hi - lo + 2 > 64LL * CM) {
+    if (lo <= hi && lane == 0) atomicOr(err, 1u);
     *C = 2;
     *dexp = 0;
-    for (int j = lane; j < 128; j += 64) ((int32_t *)cols)[j] = 0;
-    wave_sync();
+    for (int j = lane; j < 128; j += 64) dig[j] = 0;
+    __builtin_amdgcn_wave_barrier();
     return 0;
   }
-  long long width = hi - lo + 2;
-  if (width > 64LL * CM) {
-    if (lane == 0) atomicOr(err, 1u);
-    *C = 2;
-    *dexp = 0;
-    for (int j = lane; j < 128; j += 64) ((int32_t *)cols)[j] = 0;
-    wave_sync();
-    return 0;
-  }
-  const int W = (int)width;
-  for (int c = lane; c < W; c += 64) cols[c] = 0;
-  wave_sync();
+  const int W = (int)(hi - lo + 2);
+  int Cc = (W + 63) >> 6;
+  if (Cc < 2) Cc = 2;
+  *C = Cc;
+  const int c0 = lane * Cc;
+  long long v[CM];
+#pragma unroll
+  for (int j = 0; j < CM; ++j) v[j] = 0;
   if (fcols) {
     const int o = (int)(fd->base - lo);
-    for (int c = lane; c < fcols; c += 64) {
-      long long v = frame_global ? ld_relaxed(frame + c) : frame[c];
-      cols[o + c] += v;
+    if (frame_global) {
+      // branch-free: offsets outside the lane's chunk or the frame read 0
+      const __amdgpu_buffer_rsrc_t rs = dev_rsrc(frame, fcols * 8);
+#pragma unroll
+      for (int j = 0; j < CM; ++j) {
+        int fc = c0 + j - o;
+        int off = (j < Cc && fc >= 0) ? fc * 8 : 0x7ffffff0;
+        v[j] = ld_dev64(rs, off);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < CM; ++j) {
+        if (j >= Cc) break;
+        int fc = c0 + j - o;
+        if (fc >= 0 && fc < fcols) v[j] = frame[fc];
+      }
     }
-    wave_sync();
   }
   for (int a = 0; a < nadd; ++a) {
     if (as[a] == 0) continue;
     const int o = (int)(ae[a] - lo);
+    const long long sg = adds[a].sgn;
     if (adds[a].is_row) {
       const int32_t *row = adds[a].p + HDR + RPAD;
-      for (int k = lane; k < nd; k += 64) cols[o + k] += (long long)adds[a].sgn * row[k];
+#pragma unroll
+      for (int j = 0; j < CM; ++j) {
+        if (j >= Cc) break;
+        int k = c0 + j - o;
+        if (k >= 0 && k < nd) v[j] += sg * row[k];
+      }
     } else {
-      long long sh;
-      floordiv28(adds[a].p[1], &sh);
-      for (int k = lane; k < nd; k += 64) {
-        long long d = mant_bits28(adds[a].p + 2, L, (long long)DBITS * k - sh);
-        cols[o + k] += (long long)(adds[a].sgn * as[a]) * d;
+      const long long sgs = sg * as[a];
+#pragma unroll
+      for (int j = 0; j < CM; ++j) {
+        if (j >= Cc) break;
+        int k = c0 + j - o;
+        if (k >= 0 && k < nd) v[j] += sgs * (long long)mant_bits28(adds[a].p + 2, L, (long long)DBITS * k - ash[a]);
       }
     }
-    wave_sync();
   }
   bool ovf = false;
-  int sgn = wave_resolve<CM>(cols, W, (int32_t *)cols, C, &ovf);
+  int sgn = wave_resolve_regs<CM>(v, Cc, dig, &ovf);
   if (ovf && lane == 0) atomicOr(err, 1u);
   *dexp = lo;
   return sgn;
@@ -124,11 +140,13 @@ struct Carve {
   long long *tcols;    // 3 task column / digit buffers, 64*CM each
   int32_t *tq;         // 3 task quotient buffers, 64*CM each
   int32_t *tnorm;      // 3 tasks x 2 normalised values, NV each
-  int32_t *hrow;       // 3 LDS rows (Horner accumulators)
+  int32_t *hrow;       // 4 LDS rows (3 Horner accumulators, tau)
   FrameSrc *fs;        // NFR
   FrameD *fd;          // NFR + 1
   int *red;            // 64
   int *span;           // 2 NFR
+  int8_t *offs;        // NFR x maxn per-term digit offsets
+  int maxn;
   int NV;
 };
 
@@ -146,7 +164,7 @@ __device__ Carve carve(unsigned char *smem, const Inst &I) {
   c.tnorm = (int32_t *)p;
   p += (size_t)6 * NV * 4;
   c.hrow = (int32_t *)p;
-  p += (size_t)3 * I.RS * 4;
+  p += (size_t)4 * I.RS * 4;
   c.fs = (FrameSrc *)p;
   p += sizeof(FrameSrc) * NFR;
   c.fd = (FrameD *)p;
@@ -154,14 +172,18 @@ __device__ Carve carve(unsigned char *smem, const Inst &I) {
   c.red = (int *)p;
   p += 64 * 4;
   c.span = (int *)p;
+  p += 2 * NFR * 4;
+  c.maxn = (I.N + 1 + 15) & ~15;
+  c.offs = (int8_t *)p;
   return c;
 }
 
-size_t lds_bytes(int L, int RS, int WB, int CM) {
+size_t lds_bytes(int L, int N, int RS, int WB, int CM) {
   const int NV = (L + 2 + 3) & ~3;
+  const int maxn = (N + 1 + 15) & ~15;
   size_t b = (size_t)NFR * WB * 8 + (size_t)3 * 64 * CM * 8 + (size_t)3 * 64 * CM * 4 +
-             (size_t)6 * NV * 4 + (size_t)3 * RS * 4 + sizeof(FrameSrc) * NFR +
-             sizeof(FrameD) * (NFR + 1) + 64 * 4 + 2 * NFR * 4;
+             (size_t)6 * NV * 4 + (size_t)4 * RS * 4 + sizeof(FrameSrc) * NFR +
+             sizeof(FrameD) * (NFR + 1) + 64 * 4 + 2 * NFR * 4 + (size_t)NFR * maxn;
   return (b + 255) & ~(size_t)255;
 }
 
@@ -179,9 +201,10 @@ __device__ __forceinline__ void copy_norm(const int32_t *src, int32_t *dst, int 
 
 // Spin until *flag >= target (thread 0 only); gives up after ~2 s, marking
 // the error word so that the host reports it instead of hanging.
-__device__ void spin_until(const uint32_t *flag, uint32_t target, uint32_t *err) {
+__device__ void spin_until(uint32_t *flag, uint32_t target, uint32_t *err) {
   long long polls = 0;
-  while (ld_relaxed(flag) < target) {
+  // read-modify-write polls are answered at the coherence point
+  while (__hip_atomic_fetch_add(flag, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
     __builtin_amdgcn_s_sleep(2);
     if (++polls > (1LL << 25)) {
       atomicOr(err, 4u);
@@ -196,6 +219,15 @@ template <int CM>
 __device__ void finalize_task(const Inst &I, const Carve &cv, int which, int i,
                               const long long *frames, bool frames_global, uint32_t *err) {
   const int lane = lane_id();
+  const bool timed = I.prof != nullptr && which == 0 && lane == 0 && blockIdx.x == I.wg0;
+  unsigned long long tq = timed ? wall_clock64() : 0;
+  auto sub = [&](int slot) {
+    if (timed) {
+      unsigned long long t = wall_clock64();
+      atomicAdd(I.prof + slot, t - tq);
+      tq = t;
+    }
+  };
   const int L = I.L, nd = I.nd, WB = I.WB;
   long long *cols = cv.tcols + (size_t)which * 64 * I.CM;
   int32_t *dig = (int32_t *)cols;
@@ -210,8 +242,10 @@ __device__ void finalize_task(const Inst &I, const Carve &cv, int which, int i,
   if (which == 0 || which == 1) {
     // s1 (which 0) or s2 (which 1): one rounding of the exact Cauchy sum
     sgn = combine_resolve<CM>(frames + (size_t)which * WB, frames_global, &cv.fd[which], nd, L,
-                              nullptr, 0, cols, &C, &dexp, err);
+                              nullptr, 0, dig, &C, &dexp, err);
+    sub(8);
     ok &= wave_round(dig, C, sgn, dexp, false, L, tmp);
+    sub(9);
     Addend ad[2];
     int nad;
     const FrameD *fr;
@@ -232,16 +266,19 @@ __device__ void finalize_task(const Inst &I, const Carve &cv, int which, int i,
       fp = frames + (size_t)4 * WB;
       arr_out = 2;
     }
-    sgn = combine_resolve<CM>(fp, frames_global, fr, nd, L, ad, nad, cols, &C, &dexp, err);
+    sgn = combine_resolve<CM>(fp, frames_global, fr, nd, L, ad, nad, dig, &C, &dexp, err);
+    sub(10);
   } else {
     // sigma (b_i - a_i)
     sgn = combine_resolve<CM>(frames + (size_t)2 * WB, frames_global, &cv.fd[2], nd, L, nullptr,
-                              0, cols, &C, &dexp, err);
+                              0, dig, &C, &dexp, err);
     arr_out = 0;
   }
-  ok &= wave_div_round<CM>(dig, C, sgn, dexp, i + 1, L, q, res);
+  ok &= wave_div_round<CM>(dig, C, sgn, dexp, i + 1, L, nd, q, res);
+  sub(11);
   if (!ok && lane == 0) atomicOr(err, 2u);
   write_row(res, L, nd, I.RS, row_ptr(I, arr_out, i + 1), I.G > 1, lane, 64);
+  sub(12);
   if (I.coefs)
     copy_norm(res, I.coefs + ((long long)arr_out * (I.N + 1) + i + 1) * (L + 2), L, false, lane,
               64);
@@ -264,6 +301,17 @@ __global__ void __launch_bounds__(WGS) k_run(const Inst *__restrict__ insts,
   const int32_t *tau_row = I.consts + (size_t)C_TAU * RS;
   uint32_t gen = 0;
   unsigned long long nbulk = 0;
+  // phase timers (thread 0 of the leader and of workgroup 1)
+  const bool timed = I.prof != nullptr && tid == 0 && (rank == 0 || rank == 1);
+  unsigned long long *prof = timed ? I.prof + (rank == 0 ? 0 : PH_NPHASE) : nullptr;
+  unsigned long long tp = timed ? wall_clock64() : 0;
+  auto mark = [&](int phase) {
+    if (timed) {
+      unsigned long long t = wall_clock64();
+      atomicAdd(prof + phase, t - tp);
+      tp = t;
+    }
+  };
   if (leader) {
     for (int c = wave; c < NCONST; c += 4)
       write_row(I.cnorm + (size_t)c * (L + 2), L, nd, RS, I.consts + (size_t)c * RS, G > 1, lane,
@@ -294,6 +342,7 @@ __global__ void __launch_bounds__(WGS) k_run(const Inst *__restrict__ insts,
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       __syncthreads();
     }
+    mark(PH_STEP0);
 
     for (int i = 0; i < N; ++i) {
       if (tid == 0) {
@@ -306,9 +355,11 @@ __global__ void __launch_bounds__(WGS) k_run(const Inst *__restrict__ insts,
         fs[4] = FrameSrc{1, 1, I.consts + (size_t)C_NB * RS, row_ptr(I, 2, i), nullptr, nullptr, 0};
       }
       __syncthreads();
-      frame_setup(cv.fs, cv.fd, NFR, nd, RS, cv.red, err);
-      frames_accumulate(cv.fs, cv.fd, NFR, nd, RS, WB, cv.lf, rank, G, cv.span, err);
+      frame_setup(cv.fs, cv.fd, NFR, nd, RS, cv.red, cv.offs, cv.maxn, err);
+      mark(PH_SETUP);
+      frames_accumulate(cv.fs, cv.fd, NFR, nd, RS, WB, cv.lf, rank, G, cv.span, cv.offs, cv.maxn);
       __syncthreads();
+      mark(PH_ACCUM);
       ++nbulk;
       long long *gf = I.gframes + (size_t)(nbulk & 1) * NFR * WB;
       if (G > 1) {
@@ -329,14 +380,17 @@ __global__ void __launch_bounds__(WGS) k_run(const Inst *__restrict__ insts,
         if (tid == 0)
           __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
+      mark(PH_FLUSH);
       if (leader) {
         if (G > 1) {
           if (tid == 0) spin_until(arrive, (uint32_t)(G * nbulk), err);
           __syncthreads();
         }
+        mark(PH_WAIT);
         const long long *frames = G > 1 ? gf : cv.lf;
         if (wave < 3) finalize_task<(CM)>(I, cv, wave, i, frames, G > 1, err);
         __syncthreads();
+        mark(PH_FINAL);
         // clear the frames for their next use
         for (int f = 0; f < NFR; ++f) {
           int nc = cv.fd[f].nz ? frame_cols(cv.fd[f], nd) : 0;
@@ -349,27 +403,33 @@ __global__ void __launch_bounds__(WGS) k_run(const Inst *__restrict__ insts,
         __syncthreads();
         ++gen;
         if (G > 1 && tid == 0) st_relaxed(flag, gen);
+        mark(PH_CLEAR);
       } else {
         ++gen;
         if (tid == 0) spin_until(flag, gen, err);
         __syncthreads();
+        mark(PH_WAIT);
       }
     }
     if (I.mode == MODE_COEFFS) break;
 
     // Horner: h = c_N; h <- round(h tau + c_i), i = N-1..0, three chains at once
     if (leader) {
-      for (int j = tid; j < 3 * RS; j += WGS) {
+      // LDS copies of c_N (the three Horner accumulators) and of the tau row
+      for (int j = tid; j < 4 * RS; j += WGS) {
         int c = j / RS, w = j - c * RS;
-        cv.hrow[j] = row_ptr(I, c, N)[w];
+        cv.hrow[j] = c < 3 ? row_ptr(I, c, N)[w] : tau_row[w];
       }
+      const int32_t *tau_lds = cv.hrow + (size_t)3 * RS;
       __syncthreads();
       for (int i = N - 1; i >= 0; --i) {
-        if (tid < 3)
-          cv.fs[tid] = FrameSrc{1, 1, tau_row, cv.hrow + (size_t)tid * RS, nullptr, nullptr, 0};
+        if (tid == 0) {
+          for (int c = 0; c < 3; ++c)
+            cv.fs[c] = FrameSrc{1, 1, tau_lds, cv.hrow + (size_t)c * RS, nullptr, nullptr, 0};
+          frame_setup_single(cv.fs, cv.fd, 3, nd, cv.offs, cv.maxn);
+        }
         __syncthreads();
-        frame_setup(cv.fs, cv.fd, 3, nd, RS, cv.red, err);
-        frames_accumulate(cv.fs, cv.fd, 3, nd, RS, WB, cv.lf, 0, 1, cv.span, err);
+        frames_accumulate(cv.fs, cv.fd, 3, nd, RS, WB, cv.lf, 0, 1, cv.span, cv.offs, cv.maxn);
         __syncthreads();
         if (wave < 3) {
           long long *cols = cv.tcols + (size_t)wave * 64 * I.CM;
@@ -378,7 +438,7 @@ __global__ void __launch_bounds__(WGS) k_run(const Inst *__restrict__ insts,
           int C;
           long long dexp;
           int sgn = combine_resolve<CM>(cv.lf + (size_t)wave * WB, false, &cv.fd[wave], nd, L, &ad,
-                                        1, cols, &C, &dexp, err);
+                                        1, (int32_t *)cols, &C, &dexp, err);
           bool ok = wave_round((int32_t *)cols, C, sgn, dexp, false, L, h);
           if (!ok && lane == 0) atomicOr(err, 2u);
           write_row(h, L, nd, RS, cv.hrow + (size_t)wave * RS, false, lane, 64);
@@ -394,6 +454,7 @@ __global__ void __launch_bounds__(WGS) k_run(const Inst *__restrict__ insts,
           copy_norm(h, I.ckpt + ((size_t)(step + 1) * 3 + wave) * (L + 2), L, false, lane, 64);
       }
       __syncthreads();
+      mark(PH_HORNER);
     }
   }
 }

@@ -25,6 +25,17 @@ __device__ __forceinline__ void st_relaxed(long long *p, long long v) {
 __device__ __forceinline__ void st_relaxed(uint32_t *p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Device-coherent (sc1, L2-bypassing) 64-bit loads through a buffer
+// resource: unlike atomic loads they are not ordered with each other, so a
+// batch of them is in flight at once, and offsets outside [0, bytes) read 0.
+typedef int mpts_v2i __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t dev_rsrc(const void *p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, bytes, 0x00020000);
+}
+__device__ __forceinline__ long long ld_dev64(__amdgpu_buffer_rsrc_t rs, int byte_off) {
+  mpts_v2i t = __builtin_amdgcn_raw_buffer_load_b64(rs, byte_off, 0, 16 /* sc1 */);
+  return (long long)(((unsigned long long)(uint32_t)t.y << 32) | (uint32_t)t.x);
+}
 // All of this thread's outstanding global loads, stores and atomics are done.
 __device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
@@ -144,72 +155,64 @@ __device__ __forceinline__ void tile_normalize(long long (&acc)[16]) {
   }
 }
 
-// Accumulate U[mt*8 .. +8) x V[nt*8 - off .. +8) into acc (columns 0..14).
-__device__ __forceinline__ void tile_mac(long long (&acc)[16], const int32_t *U, const int32_t *V,
-                                         int mt, int nt, int off) {
-  const int32_t *u = U + HDR + RPAD + mt * TQ;
-  const int32_t *v = V + HDR + RPAD + nt * TQ - off;
-  int32_t uu[TQ], vv[TQ];
-#pragma unroll
-  for (int r = 0; r < TQ; ++r) uu[r] = u[r];
-#pragma unroll
-  for (int s = 0; s < TQ; ++s) vv[s] = v[s];
-#pragma unroll
-  for (int r = 0; r < TQ; ++r)
-#pragma unroll
-    for (int s = 0; s < TQ; ++s) acc[r + s] += (long long)uu[r] * (long long)vv[s];
-}
-
 // Per-workgroup frame setup: exponent base and spread of each frame's
-// nonzero terms (a workgroup reduction for Cauchy frames).  Every thread of
-// the workgroup calls this; results land in fd[0..nf).  red: 8*64 ints.
+// nonzero terms (one workgroup reduction for all frames), and the table of
+// per-term digit offsets offs[f * maxn + k] (0 for zero terms, whose rows
+// are all-zero digits).  Every thread of the workgroup calls this.
+// red: 4 waves x 2 NFR ints.
 __device__ void frame_setup(const FrameSrc *fs, FrameD *fd, int nf, int nd, int RS, int *red,
-                            uint32_t *err) {
+                            int8_t *offs, int maxn, uint32_t *err) {
   const int tid = threadIdx.x;
   const int MT = (nd + TQ - 1) / TQ;
-  for (int f = 0; f < nf; ++f) {
-    int mn = 0x7fffffff, mx = -0x7fffffff;
-    for (int k = tid; k < fs[f].n; k += WGS) {
-      const int32_t *U, *V;
-      frame_term(fs[f], k, RS, &U, &V);
-      if (U[1] != 0 && V[1] != 0) {
-        int e = U[0] + V[0];
-        mn = min(mn, e);
-        mx = max(mx, e);
+  int mn[NFR], mx[NFR];
+#pragma unroll
+  for (int f = 0; f < NFR; ++f) {
+    mn[f] = 0x7fffffff;
+    mx[f] = -0x7fffffff;
+    if (f < nf) {
+      for (int k = tid; k < fs[f].n; k += WGS) {
+        const int32_t *U, *V;
+        frame_term(fs[f], k, RS, &U, &V);
+        if (U[1] != 0 && V[1] != 0) {
+          int e = U[0] + V[0];
+          mn[f] = min(mn[f], e);
+          mx[f] = max(mx[f], e);
+        }
       }
     }
-    // workgroup min / max
+#pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
-      mn = min(mn, __shfl_xor(mn, o, 64));
-      mx = max(mx, __shfl_xor(mx, o, 64));
+      mn[f] = min(mn[f], __shfl_xor(mn[f], o, 64));
+      mx[f] = max(mx[f], __shfl_xor(mx[f], o, 64));
     }
     if ((tid & 63) == 0) {
-      red[2 * (tid >> 6)] = mn;
-      red[2 * (tid >> 6) + 1] = mx;
+      red[(tid >> 6) * 2 * NFR + 2 * f] = mn[f];
+      red[(tid >> 6) * 2 * NFR + 2 * f + 1] = mx[f];
     }
-    __syncthreads();
-    if (tid == 0) {
-      int a = red[0], b = red[1];
-      for (int w = 1; w < WGS / 64; ++w) {
-        a = min(a, red[2 * w]);
-        b = max(b, red[2 * w + 1]);
-      }
-      FrameD d;
-      d.n = fs[f].n;
-      d.nz = (a <= b) ? 1 : 0;
-      d.base = d.nz ? a : 0;
-      int S = d.nz ? (b - a) : 0;
-      if (S > SMAX) {
-        atomicOr(err, 1u);
-        S = SMAX;
-      }
-      d.S = S;
-      d.NT = (nd + S + TQ - 1) / TQ;
-      d.pad = MT;
-      fd[f] = d;
-    }
-    __syncthreads();
   }
+  __syncthreads();
+  if (tid < nf) {
+    const int f = tid;
+    int a = red[2 * f], b = red[2 * f + 1];
+    for (int w = 1; w < WGS / 64; ++w) {
+      a = min(a, red[w * 2 * NFR + 2 * f]);
+      b = max(b, red[w * 2 * NFR + 2 * f + 1]);
+    }
+    FrameD d;
+    d.n = fs[f].n;
+    d.nz = (a <= b) ? 1 : 0;
+    d.base = d.nz ? a : 0;
+    int S = d.nz ? (b - a) : 0;
+    if (S > SMAX) {
+      atomicOr(err, 1u);
+      S = SMAX;
+    }
+    d.S = S;
+    d.NT = (nd + S + TQ - 1) / TQ;
+    d.pad = MT;
+    fd[f] = d;
+  }
+  __syncthreads();
   if (tid == 0) {
     long long c = 0;
     for (int f = 0; f < nf; ++f) {
@@ -218,7 +221,43 @@ __device__ void frame_setup(const FrameSrc *fs, FrameD *fd, int nf, int nd, int 
     }
     fd[nf].cost0 = c;
   }
+  for (int f = 0; f < nf; ++f) {
+    const int base = fd[f].base, S = fd[f].S;
+    for (int k = tid; k < fs[f].n; k += WGS) {
+      const int32_t *U, *V;
+      frame_term(fs[f], k, RS, &U, &V);
+      int off = 0;
+      if (U[1] != 0 && V[1] != 0) {
+        off = U[0] + V[0] - base;
+        if (off < 0 || off > S) off = 0;  // only after a spread error (already flagged)
+      }
+      offs[f * maxn + k] = (int8_t)off;
+    }
+  }
   __syncthreads();
+}
+
+// Frame setup for frames of exactly one term each (the Horner products):
+// thread 0 only, no workgroup reduction.
+__device__ void frame_setup_single(const FrameSrc *fs, FrameD *fd, int nf, int nd,
+                                   int8_t *offs, int maxn) {
+  const int MT = (nd + TQ - 1) / TQ;
+  long long c = 0;
+  for (int f = 0; f < nf; ++f) {
+    FrameD d;
+    const int32_t *U = fs[f].U0, *V = fs[f].V0;
+    d.n = 1;
+    d.nz = (U[1] != 0 && V[1] != 0) ? 1 : 0;
+    d.base = d.nz ? U[0] + V[0] : 0;
+    d.S = 0;
+    d.NT = MT;
+    d.pad = MT;
+    d.cost0 = c;
+    if (d.nz) c += (long long)MT * MT;
+    fd[f] = d;
+    offs[f * maxn] = 0;
+  }
+  fd[nf].cost0 = c;
 }
 
 // Columns spanned by frame f's tiles: [0, (MT + NT) * 8 + 8).
@@ -227,23 +266,56 @@ __device__ __forceinline__ int frame_cols(const FrameD &d, int nd) {
   return (MT + d.NT) * TQ + TQ;
 }
 
+__device__ __forceinline__ void tile_load(int32_t (&uu)[TQ], int32_t (&vv)[TQ], const int32_t *U,
+                                          const int32_t *V, int mt, int nt, int off) {
+  const int32_t *u = U + HDR + RPAD + mt * TQ;
+  const int32_t *v = V + HDR + RPAD + nt * TQ - off;
+#pragma unroll
+  for (int r = 0; r < TQ; ++r) uu[r] = u[r];
+#pragma unroll
+  for (int r = 0; r < TQ; ++r) vv[r] = v[r];
+}
+
+__device__ __forceinline__ void tile_fma(long long (&acc)[16], const int32_t (&uu)[TQ],
+                                         const int32_t (&vv)[TQ]) {
+#pragma unroll
+  for (int r = 0; r < TQ; ++r)
+#pragma unroll
+    for (int s = 0; s < TQ; ++s) acc[r + s] += (long long)uu[r] * (long long)vv[s];
+}
+
+__device__ __forceinline__ void acc_flush(long long (&acc)[16], long long *col) {
+  tile_normalize(acc);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    if (acc[r] != 0) atomicAdd((unsigned long long *)(col + r), (unsigned long long)acc[r]);
+    acc[r] = 0;
+  }
+}
+
 // The workgroup `rank` of `G` accumulates its share of all frames' tiles
-// into the LDS column arrays lf[f * WB + c].  Tiles are dealt out in
-// contiguous ranges of equal cost (tiles x terms); inside the workgroup,
-// threads split each tile's terms.  Returns through span[2f], span[2f+1]
-// the column range this workgroup touched in frame f (empty: lo >= hi).
+// into the LDS column arrays lf[f * WB + c].  Tiles are dealt to workgroups
+// in contiguous ranges (anti-diagonal order) of equal cost (tiles x terms).
+// Inside the workgroup the (tile, term) pairs are split evenly over the
+// threads in tile-major order, so a thread walks consecutive terms of
+// consecutive tiles; it keeps its 16 column sums in registers while it stays
+// on one anti-diagonal and adds them into LDS when it leaves it.  The next
+// term's digits are loaded before the current term's products are formed.
+// Returns through span[2f], span[2f+1] the column range this workgroup
+// touched in frame f (empty: lo >= hi).
 __device__ void frames_accumulate(const FrameSrc *fs, const FrameD *fd, int nf, int nd, int RS,
                                   int WB, long long *lf, int rank, int G, int *span,
-                                  uint32_t *err) {
+                                  const int8_t *offs, int maxn) {
   const int tid = threadIdx.x;
   const int MT = (nd + TQ - 1) / TQ;
   const long long C = fd[nf].cost0;
   const long long lo = C * rank / G, hi = C * (rank + 1) / G;
-  // per-frame tile range [t0, t1)
-  int t0[NFR], t1[NFR], nT = 0;
-  for (int f = 0; f < nf; ++f) {
+  int t0[NFR], t1[NFR];
+  long long w = 0;
+#pragma unroll
+  for (int f = 0; f < NFR; ++f) {
     t0[f] = t1[f] = 0;
-    if (!fd[f].nz || fd[f].n == 0) continue;
+    if (f >= nf || !fd[f].nz || fd[f].n == 0) continue;
     long long pre = fd[f].cost0;
     long long n = fd[f].n;
     long long T = (long long)MT * fd[f].NT;
@@ -254,60 +326,12 @@ __device__ void frames_accumulate(const FrameSrc *fs, const FrameD *fd, int nf, 
     if (tb > T) tb = T;
     t0[f] = (int)ta;
     t1[f] = (int)tb;
-    nT += (int)(tb - ta);
+    w += (tb - ta) * n;
   }
   if (tid < 2 * nf) span[tid] = 0;
-  if (nT == 0) return;
-  for (int base = 0; base < nT; base += WGS) {
-    int cnt = min(nT - base, WGS);
-    int tt, slot, lam;
-    if (cnt >= WGS) {
-      tt = base + tid;
-      slot = 0;
-      lam = 1;
-    } else {
-      tt = base + tid % cnt;
-      slot = tid / cnt;
-      lam = (WGS - 1 - tid % cnt) / cnt + 1;
-    }
-    if (tt >= nT) continue;
-    // which frame
-    int f = 0, loc = tt;
-    while (f < nf && loc >= t1[f] - t0[f]) {
-      loc -= t1[f] - t0[f];
-      ++f;
-    }
-    int t = t0[f] + loc;
-    int mt, nt;
-    tile_coords(t, MT, fd[f].NT, &mt, &nt);
-    long long acc[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = 0;
-    const int base_e = fd[f].base, S = fd[f].S;
-    int since = 0;
-    for (int k = slot; k < fd[f].n; k += lam) {
-      const int32_t *U, *V;
-      frame_term(fs[f], k, RS, &U, &V);
-      int sU = U[1], sV = V[1];
-      if (sU == 0 || sV == 0) continue;
-      int off = U[0] + V[0] - base_e;
-      if (off < 0 || off > S) continue;  // only after a spread error
-      tile_mac(acc, U, V, mt, nt, off);
-      if (++since == FLUSH_TERMS) {
-        tile_normalize(acc);
-        since = 0;
-      }
-    }
-    tile_normalize(acc);
-    long long *col = lf + (long long)f * WB + (mt + nt) * TQ;
-#pragma unroll
-    for (int r = 0; r < 16; ++r)
-      if (acc[r] != 0) atomicAdd((unsigned long long *)(col + r), (unsigned long long)acc[r]);
-  }
-  (void)err;
-  // column spans touched (anti-diagonals of the first and last tile)
+  __syncthreads();
   if (tid < nf) {
-    int f = tid;
+    const int f = tid;
     if (t1[f] > t0[f]) {
       int mt, nt;
       tile_coords(t0[f], MT, fd[f].NT, &mt, &nt);
@@ -318,6 +342,70 @@ __device__ void frames_accumulate(const FrameSrc *fs, const FrameD *fd, int nf, 
       span[2 * f + 1] = max(dlo, dhi) * TQ + 2 * TQ;
     }
   }
+  if (w == 0) return;
+  long long q = w * tid / WGS;
+  const long long qend = w * (tid + 1) / WGS;
+  long long acc[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0;
+  int cur_f = -1, cur_d = -1;
+  int since = 0;
+  int f = 0;
+  long long fstart = 0;  // first item of frame f in the workgroup's list
+  while (q < qend) {
+    // frame of item q
+    while (f < nf && q >= fstart + (long long)(t1[f] - t0[f]) * fd[f].n) {
+      fstart += (long long)(t1[f] - t0[f]) * fd[f].n;
+      ++f;
+    }
+    const int n = fd[f].n;
+    const long long rel = q - fstart;
+    const int t = t0[f] + (int)(rel / n);
+    const int k0 = (int)(rel % n);
+    const long long seg_end = min(qend, fstart + (long long)(t - t0[f] + 1) * n);
+    const int k1 = k0 + (int)(seg_end - q);
+    int mt, nt;
+    tile_coords(t, MT, fd[f].NT, &mt, &nt);
+    const int d = mt + nt;
+    if (f != cur_f || d != cur_d) {
+      if (cur_f >= 0) acc_flush(acc, lf + (size_t)cur_f * WB + cur_d * TQ);
+      cur_f = f;
+      cur_d = d;
+      since = 0;
+    }
+    const int8_t *of = offs + f * maxn;
+    const FrameSrc src = fs[f];
+    int32_t ua[TQ], va[TQ], ub[TQ], vb[TQ];
+    const int32_t *U, *V;
+    frame_term(src, k0, RS, &U, &V);
+    tile_load(ua, va, U, V, mt, nt, of[k0]);
+    int k = k0;
+    while (k < k1) {
+      if (k + 1 < k1) {
+        frame_term(src, k + 1, RS, &U, &V);
+        tile_load(ub, vb, U, V, mt, nt, of[k + 1]);
+      }
+      tile_fma(acc, ua, va);
+      if (++since == FLUSH_TERMS) {
+        tile_normalize(acc);
+        since = 0;
+      }
+      ++k;
+      if (k >= k1) break;
+      if (k + 1 < k1) {
+        frame_term(src, k + 1, RS, &U, &V);
+        tile_load(ua, va, U, V, mt, nt, of[k + 1]);
+      }
+      tile_fma(acc, ub, vb);
+      if (++since == FLUSH_TERMS) {
+        tile_normalize(acc);
+        since = 0;
+      }
+      ++k;
+    }
+    q = seg_end;
+  }
+  if (cur_f >= 0) acc_flush(acc, lf + (size_t)cur_f * WB + cur_d * TQ);
 }
 
 }  // namespace mpts

@@ -39,12 +39,12 @@ template <int CM>
 __device__ __forceinline__ long long chunk_add(long long (&v)[CM], int C, long long x) {
   // v += x at the chunk bottom (x >= 0); returns the carry out of the chunk
 #pragma unroll
-  for (int j = 0; j < CM; ++j)
-    if (j < C) {
-      long long t = v[j] + x;
-      v[j] = t & DMASK;
-      x = t >> DBITS;
-    }
+  for (int j = 0; j < CM; ++j) {
+    if (j >= C) break;
+    long long t = v[j] + x;
+    v[j] = t & DMASK;
+    x = t >> DBITS;
+  }
   return x;
 }
 
@@ -52,12 +52,12 @@ template <int CM>
 __device__ __forceinline__ long long chunk_sub(long long (&v)[CM], int C, long long x) {
   // v -= x at the chunk bottom (x >= 0); returns the borrow out of the chunk
 #pragma unroll
-  for (int j = 0; j < CM; ++j)
-    if (j < C) {
-      long long t = v[j] - x;
-      v[j] = t & DMASK;
-      x = -(t >> DBITS);
-    }
+  for (int j = 0; j < CM; ++j) {
+    if (j >= C) break;
+    long long t = v[j] - x;
+    v[j] = t & DMASK;
+    x = -(t >> DBITS);
+  }
   return x;
 }
 
@@ -65,8 +65,10 @@ template <int CM>
 __device__ __forceinline__ bool chunk_all(const long long (&v)[CM], int C, long long val) {
   bool all = true;
 #pragma unroll
-  for (int j = 0; j < CM; ++j)
-    if (j < C) all &= (v[j] == val);
+  for (int j = 0; j < CM; ++j) {
+    if (j >= C) break;
+    all &= (v[j] == val);
+  }
   return all;
 }
 
@@ -87,31 +89,23 @@ __device__ __forceinline__ bool wave_borrow(long long (&v)[CM], int C, bool b) {
   return top;
 }
 
-// Resolve n signed 64-bit column sums cols[0..n) (value sum cols[c] 2^(28c),
-// |cols[c]| < 2^62) into a sign and a magnitude of 64*C digits in [0, 2^28),
-// written to dig[0..64*C).  cols and dig may be the same LDS memory (every
-// lane reads its chunk before writing).  Returns -1, 0 or +1; *ovf is set
-// when the magnitude does not fit 64*C digits.
+// Resolve signed 64-bit column sums held in registers, lane l owning
+// columns [l*C, l*C + C) (value sum v 2^(28 c), |v| < 2^62, C >= 2), into a
+// sign and a magnitude of 64*C digits in [0, 2^28) written to dig[0..64*C).
+// Returns -1, 0 or +1; *ovf is set when the magnitude does not fit.
 template <int CM>
-__device__ int wave_resolve(const long long *cols, int n, int32_t *dig, int *Cout, bool *ovf) {
+__device__ int wave_resolve_regs(long long (&v)[CM], int C, int32_t *dig, bool *ovf) {
   const int lane = lane_id();
-  int C = (n + 63) >> 6;
-  if (C < 2) C = 2;
-  *Cout = C;
-  long long v[CM];
   const int lo = lane * C;
-#pragma unroll
-  for (int j = 0; j < CM; ++j) v[j] = (j < C && lo + j < n) ? cols[lo + j] : 0;
-  __builtin_amdgcn_wave_barrier();
   // local carry propagation: digits in [0, 2^28) and a signed chunk carry
   long long carry = 0;
 #pragma unroll
-  for (int j = 0; j < CM; ++j)
-    if (j < C) {
-      long long t = v[j] + carry;
-      v[j] = t & DMASK;
-      carry = t >> DBITS;
-    }
+  for (int j = 0; j < CM; ++j) {
+    if (j >= C) break;
+    long long t = v[j] + carry;
+    v[j] = t & DMASK;
+    carry = t >> DBITS;
+  }
   long long top = __shfl(carry, 63, 64);
   long long cin = shfl_up1(carry);
   // add the positive part of the incoming carry, then subtract the negative part
@@ -126,11 +120,12 @@ __device__ int wave_resolve(const long long *cols, int n, int32_t *dig, int *Cou
   } else if (T == -1) {
     // negative: magnitude = 2^(28*64C) - v
 #pragma unroll
-    for (int j = 0; j < CM; ++j)
-      if (j < C) v[j] = DMASK - v[j];
+    for (int j = 0; j < CM; ++j) {
+      if (j >= C) break;
+      v[j] = DMASK - v[j];
+    }
     long long c0 = (lane == 0) ? chunk_add<CM>(v, C, 1) : 0;
-    bool tt = wave_carry<CM>(v, C, c0 != 0);
-    (void)tt;
+    (void)wave_carry<CM>(v, C, c0 != 0);
     sign = -1;
   } else {
     *ovf = true;
@@ -139,8 +134,10 @@ __device__ int wave_resolve(const long long *cols, int n, int32_t *dig, int *Cou
   bool nz = !chunk_all<CM>(v, C, 0);
   if (__ballot(nz) == 0ull) sign = 0;
 #pragma unroll
-  for (int j = 0; j < CM; ++j)
-    if (j < C) dig[lo + j] = (int32_t)v[j];
+  for (int j = 0; j < CM; ++j) {
+    if (j >= C) break;
+    dig[lo + j] = (int32_t)v[j];
+  }
   __builtin_amdgcn_wave_barrier();
   return sign;
 }
@@ -213,8 +210,10 @@ __device__ bool wave_round(const int32_t *dig, int C, int sign, long long dexp, 
   uint32_t mv[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
+    mv[j] = 0u;
+    if (j >= CL) continue;
     int li = lane * CL + j;
-    mv[j] = (j < CL && li < L) ? dig_bits32(dig, n, sh + 32LL * li) : 0u;
+    if (li < L) mv[j] = dig_bits32(dig, n, sh + 32LL * li);
   }
   bool lsb = (__shfl((int)(mv[0] & 1u), 0, 64) & 1) != 0;
   bool up = rbit && (sticky || lsb);
@@ -290,29 +289,42 @@ __device__ __forceinline__ long long divmod_small(long long val, int d, double i
 }
 
 // Round (sign * mag * 2^(28 dexp)) / d to p bits.  mag = dig[0..64C) is a
-// magnitude digit vector; the quotient is formed with enough extra low
-// digits that it carries at least p + 2 bits, and the final remainder
-// becomes the sticky bit.  q is scratch of CM*64 digits.
+// magnitude digit vector.  Only its top nd+3 digits (nd = digits of a p-bit
+// row) enter the division: the quotient then carries at least p + 2 bits,
+// and the digits below can only make the value larger by less than one unit
+// of the quotient's last digit, so they count as sticky bits, as does the
+// final remainder.  Short magnitudes are extended with zero digits at the
+// bottom until the quotient has p + 2 bits.  q is scratch of 64*CM digits.
 template <int CM>
 __device__ bool wave_div_round(const int32_t *dig, int C, int sign, long long dexp, int d, int L,
-                               int32_t *q, int32_t *out) {
+                               int nd, int32_t *q, int32_t *out) {
   const int lane = lane_id();
   int t = wave_top_digit(dig, C);
   if (t < 0 || sign == 0) return wave_round(dig, C, 0, 0, false, L, out);
   uint32_t dt = (uint32_t)dig[t];
-  long long bits = (long long)t * DBITS + (32 - __clz(dt));  // bit length
+  const int keep = nd + 3;
+  int lowcut = t + 1 - keep;
+  if (lowcut < 0) lowcut = 0;
+  // digits below lowcut only matter through "nonzero"
+  bool lz = false;
+  for (int j = 0; j < C; ++j) {
+    int k = lane * C + j;
+    if (k < lowcut) lz |= (dig[k] != 0);
+  }
+  const bool low_nz = __ballot(lz) != 0ull;
+  long long bits = (long long)(t - lowcut) * DBITS + (32 - __clz(dt));  // window bit length
   long long need = 32LL * L + 16;
   int m = 0;
   if (bits < need) m = (int)((need - bits + DBITS - 1) / DBITS);
-  int n2 = t + 1 + m;  // dividend digits: dig[0..t] shifted up by m
+  int n2 = t + 1 - lowcut + m;  // dividend digits: dig[lowcut..t] shifted up by m
   int C2 = (n2 + 63) >> 6;
   if (C2 < 1) C2 = 1;
   const double inv = 1.0 / (double)d;
   // chunk remainder from the top
   long long r = 0;
   for (int j = C2 - 1; j >= 0; --j) {
-    int k = lane * C2 + j - m;
-    long long x = (k >= 0 && k <= t) ? (long long)(uint32_t)dig[k] : 0;
+    int k = lane * C2 + j - m + lowcut;
+    long long x = (k >= lowcut && k <= t) ? (long long)(uint32_t)dig[k] : 0;
     divmod_small((r << DBITS) | x, d, inv, &r);
   }
   // P = 2^(28 C2) mod d
@@ -324,9 +336,8 @@ __device__ bool wave_div_round(const int32_t *dig, int C, int sign, long long de
     long long A2 = __shfl_down(A, s, 64);
     long long B2 = __shfl_down(Bv, s, 64);
     if (lane + s < 64) {
-      long long nb;
+      long long nb, na;
       divmod_small(A * B2 + Bv, d, inv, &nb);
-      long long na;
       divmod_small(A * A2, d, inv, &na);
       A = na;
       Bv = nb;
@@ -337,14 +348,14 @@ __device__ bool wave_div_round(const int32_t *dig, int C, int sign, long long de
   // quotient digits
   r = rin;
   for (int j = C2 - 1; j >= 0; --j) {
-    int k = lane * C2 + j - m;
-    long long x = (k >= 0 && k <= t) ? (long long)(uint32_t)dig[k] : 0;
+    int k = lane * C2 + j - m + lowcut;
+    long long x = (k >= lowcut && k <= t) ? (long long)(uint32_t)dig[k] : 0;
     long long qq = divmod_small((r << DBITS) | x, d, inv, &r);
     q[lane * C2 + j] = (int32_t)qq;
   }
-  bool sticky = __shfl((int)(r != 0), 0, 64) != 0;
+  bool sticky = (__shfl((int)(r != 0), 0, 64) != 0) || low_nz;
   __builtin_amdgcn_wave_barrier();
-  return wave_round(q, C2, sign, dexp - m, sticky, L, out);
+  return wave_round(q, C2, sign, dexp + lowcut - m, sticky, L, out);
 }
 
 }  // namespace mpts
