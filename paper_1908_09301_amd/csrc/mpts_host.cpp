@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -450,8 +451,6 @@ int run_single(mpts_ctx *c, int mode, long long nsteps, const void *x0_dev, void
   if (e != hipSuccess) return hip_err(c, e, "clear");
   e = launch_clear(base + l.gframes, (size_t)2 * NFR * c->WB * 8, s);
   if (e != hipSuccess) return hip_err(c, e, "clear");
-  e = launch_clear(base + l.rows, (size_t)3 * (c->N + 1) * c->RS * 4, s);
-  if (e != hipSuccess) return hip_err(c, e, "clear");
   e = hipMemcpyAsync(base + l.cnorm, c->cn.data(), c->cn.size() * 4, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_err(c, e, "copy constants");
   size_t sb = (size_t)3 * (c->L + 2) * 4;
@@ -483,7 +482,8 @@ int run_single(mpts_ctx *c, int mode, long long nsteps, const void *x0_dev, void
   if (e != hipSuccess) return hip_err(c, e, "copy descriptor");
   e = launch_clear(base + l.wgmap, (size_t)G * 4, s);
   if (e != hipSuccess) return hip_err(c, e, "clear");
-  e = launch_run((const Inst *)(base + l.inst), (const int *)(base + l.wgmap), G, c->CM, c->lds, s);
+  e = launch_run((const Inst *)(base + l.inst), (const int *)(base + l.wgmap), G, c->CM, c->lds, s,
+                 true);
   if (e != hipSuccess) return hip_err(c, e, "launch");
   if (xout_dev) {
     e = hipMemcpyAsync(xout_dev, base + l.state, sb, hipMemcpyDeviceToDevice, s);
@@ -520,6 +520,184 @@ int read_status(mpts_ctx *c, void *ws, hipStream_t s) {
   if (w & 4u) return set_err(c, MPTS_EHIP, "device synchronisation timed out");
   if (w & 3u) return set_err(c, MPTS_ERANGE, "exact sum outside the device window or exponent overflow");
   return MPTS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Batched ensembles: one launch, trajectory t on G[t] workgroups.
+namespace {
+
+struct BatchLayout {
+  std::vector<size_t> region;      // byte offset of each trajectory's region
+  std::vector<size_t> state_off;   // int32 offset of each packed state in `states`
+  size_t insts = 0, wgmap = 0, states = 0, total = 0;
+  size_t states_words = 0;
+  size_t max_single = 0;           // largest single-trajectory layout (autotune probes)
+  int CM = 4;
+  size_t lds = 0;
+};
+
+int batch_layout(mpts_ctx *const *ctxs, int count, BatchLayout &bl) {
+  bl = BatchLayout();
+  size_t o = 0;
+  bl.insts = o;
+  o = al(o + (size_t)count * sizeof(Inst));
+  bl.wgmap = o;
+  o = al(o + (size_t)kMaxWG * 4);
+  bl.states = o;
+  for (int t = 0; t < count; ++t) {
+    bl.state_off.push_back(bl.states_words);
+    bl.states_words += (size_t)3 * (ctxs[t]->L + 2);
+  }
+  o = al(o + bl.states_words * 4);
+  int maxnd = 0;
+  for (int t = 0; t < count; ++t) {
+    mpts_ctx *c = ctxs[t];
+    bl.region.push_back(o);
+    o = al(o + layout(c, 0, false, 1).inst);
+    bl.max_single = std::max(bl.max_single, layout(c, 2, false, kMaxWG).total);
+    maxnd = std::max(maxnd, c->nd);
+  }
+  bl.total = std::max(o, bl.max_single);
+  bl.CM = choose_cm(maxnd);
+  if (bl.CM < 0) return MPTS_EUNSUPPORTED;
+  for (int t = 0; t < count; ++t) {
+    mpts_ctx *c = ctxs[t];
+    bl.lds = std::max(bl.lds, lds_bytes(c->L, c->N, c->RS, c->WB, bl.CM));
+  }
+  return MPTS_OK;
+}
+
+// Measured milliseconds per step of one trajectory class at 1, 2, 4, 8
+// workgroups (filled by the autotuner; keyed by L and N).
+std::map<std::pair<int, int>, std::vector<double>> g_tune;
+
+double model_ms(const mpts_ctx *c, int G) {
+  // latency per coefficient index (single workgroup / group synchronisation)
+  // plus the product work spread over G workgroups
+  const double lat = G == 1 ? 0.012 : 0.045;
+  const double digit_macs = (double)c->N * (c->N + 5) * c->nd * (double)c->nd;
+  const double wg_rate = 2.6e13 / 256.0 * 0.25;  // sustained digit-MAC/s of one workgroup
+  return (c->N * 2 * lat) + digit_macs / (G * wg_rate) * 1e3;
+}
+
+double step_ms(const mpts_ctx *c, int G) {
+  auto it = g_tune.find({c->L, c->N});
+  if (it != g_tune.end()) {
+    int k = G == 1 ? 0 : G == 2 ? 1 : G == 4 ? 2 : 3;
+    if (it->second[k] > 0) return it->second[k];
+  }
+  return model_ms(c, G);
+}
+
+// Time a few steps of one trajectory of context c at each of 1, 2, 4, 8
+// workgroups, in the caller's workspace, and record them in g_tune.
+int autotune_class(mpts_ctx *c, void *ws, size_t ws_bytes, hipStream_t s) {
+  if (g_tune.count({c->L, c->N})) return MPTS_OK;
+  std::vector<double> ms(4, -1.0);
+  std::vector<int32_t> x((size_t)3 * (c->L + 2), 0);
+  // a generic nonzero state: (1, 2, 3)
+  for (int k = 0; k < 3; ++k) {
+    Rational q;
+    q.num = Big{(uint32_t)(k + 1)};
+    q.den = Big{1u};
+    std::vector<int32_t> nv;
+    round_rational(q, 0, c->L, nv);
+    std::copy(nv.begin(), nv.end(), x.begin() + (size_t)k * (c->L + 2));
+  }
+  const int saved = c->wgs;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return set_err(c, MPTS_EHIP, "event");
+  const int gs[4] = {1, 2, 4, 8};
+  int rc = MPTS_OK;
+  for (int k = 0; k < 4 && rc == MPTS_OK; ++k) {
+    c->wgs = gs[k];
+    const long long steps = 2;
+    rc = run_single(c, MODE_INTEGRATE, 1, nullptr, nullptr, nullptr, ws, ws_bytes, s, true, x.data());
+    if (rc) break;
+    (void)hipEventRecord(e0, s);
+    rc = run_single(c, MODE_INTEGRATE, steps, nullptr, nullptr, nullptr, ws, ws_bytes, s, true,
+                    x.data());
+    (void)hipEventRecord(e1, s);
+    if (rc) break;
+    (void)hipEventSynchronize(e1);
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, e0, e1);
+    ms[k] = t / steps;
+  }
+  c->wgs = saved;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  g_tune[{c->L, c->N}] = ms;
+  return MPTS_OK;
+}
+
+// Workgroups per trajectory: start with one each and repeatedly double the
+// group of the trajectory with the longest predicted run while the launch
+// still fits on the device at once.
+int plan_batch(mpts_ctx *const *ctxs, int count, const int64_t *nsteps, const BatchLayout &bl,
+               bool autotune, void *ws, size_t ws_bytes, hipStream_t s, std::vector<int> &G) {
+  mpts_ctx *c0 = ctxs[0];
+  int per_cu = 0;
+  if (max_coresident(bl.CM, bl.lds, &per_cu) != 0 || per_cu < 1)
+    return set_err(c0, MPTS_EUNSUPPORTED, "kernel does not fit one compute unit");
+  const int cap = std::min(c0->cus * per_cu, kMaxWG);
+  if (count > cap) return set_err(c0, MPTS_EUNSUPPORTED, "more trajectories than resident workgroups");
+  if (autotune)
+    for (int t = 0; t < count; ++t) {
+      int st = autotune_class(ctxs[t], ws, ws_bytes, s);
+      if (st) return st;
+    }
+  G.assign((size_t)count, 1);
+  int used = count;
+  for (;;) {
+    int worst = -1;
+    double tw = -1.0;
+    for (int t = 0; t < count; ++t) {
+      double tt = nsteps[t] * step_ms(ctxs[t], G[t]);
+      if (tt > tw) {
+        tw = tt;
+        worst = t;
+      }
+    }
+    if (worst < 0 || G[worst] >= 8) break;
+    int ng = G[worst] * 2;
+    if (used + (ng - G[worst]) > cap) break;
+    if (step_ms(ctxs[worst], ng) >= step_ms(ctxs[worst], G[worst])) break;
+    used += ng - G[worst];
+    G[worst] = ng;
+  }
+  return MPTS_OK;
+}
+
+struct GraphKey {
+  void *ws = nullptr;
+  std::vector<mpts_ctx *> ctxs;
+  std::vector<int64_t> nsteps;
+  std::vector<int> G;
+  bool operator<(const GraphKey &o) const {
+    if (ws != o.ws) return ws < o.ws;
+    if (ctxs != o.ctxs) return ctxs < o.ctxs;
+    if (nsteps != o.nsteps) return nsteps < o.nsteps;
+    return G < o.G;
+  }
+};
+std::map<GraphKey, hipGraphExec_t> g_graphs;
+
+hipGraphExec_t graph_lookup(const GraphKey &k) {
+  auto it = g_graphs.find(k);
+  return it == g_graphs.end() ? nullptr : it->second;
+}
+
+void graph_store(const GraphKey &k, hipGraphExec_t e) {
+  if (g_graphs.size() > 64) {
+    for (auto &kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
+    g_graphs.clear();
+  }
+  g_graphs[k] = e;
 }
 
 }  // namespace
@@ -715,16 +893,159 @@ int mpts_coefficients(mpts_ctx *c, const mpts_bf x0[3], mpts_bf *alpha, mpts_bf 
 
 int mpts_batch_workspace_bytes(mpts_ctx *const *ctxs, int32_t count, const int64_t *nsteps,
                                uint32_t flags, size_t *bytes) {
-  (void)ctxs; (void)count; (void)nsteps; (void)flags; (void)bytes;
-  return MPTS_EUNSUPPORTED;
+  if (!ctxs || count < 1 || !nsteps || !bytes) return MPTS_EINVAL;
+  (void)flags;
+  BatchLayout bl;
+  int st = batch_layout(ctxs, count, bl);
+  if (st) return st;
+  *bytes = bl.total;
+  return MPTS_OK;
 }
 
 int mpts_integrate_batch(mpts_ctx *const *ctxs, int32_t count, const mpts_bf *x0,
                          const int64_t *nsteps, mpts_bf *x_out, void *ws, size_t ws_bytes,
                          void *stream, uint32_t flags) {
-  (void)ctxs; (void)count; (void)x0; (void)nsteps; (void)x_out; (void)ws; (void)ws_bytes;
-  (void)stream; (void)flags;
-  return MPTS_EUNSUPPORTED;
+  if (!ctxs || count < 1 || !x0 || !nsteps || !x_out || !ws) return MPTS_EINVAL;
+  for (int t = 0; t < count; ++t)
+    if (!ctxs[t] || nsteps[t] < 0) return MPTS_EINVAL;
+  mpts_ctx *c0 = ctxs[0];
+  hipStream_t s = (hipStream_t)stream;
+  int st = check_device(c0);
+  if (st) return st;
+  for (int t = 1; t < count; ++t) {
+    st = check_device(ctxs[t]);
+    if (st) return st;
+  }
+  BatchLayout bl;
+  st = batch_layout(ctxs, count, bl);
+  if (st) return set_err(c0, st, "batch layout");
+  if (ws_bytes < bl.total) return set_err(c0, MPTS_ENOSPC, "workspace too small");
+  char *base = (char *)ws;
+  // schedule: workgroups per trajectory
+  std::vector<int> G;
+  st = plan_batch(ctxs, count, nsteps, bl, (flags & MPTS_AUTOTUNE) != 0, ws, ws_bytes, s, G);
+  if (st) return st;
+  int total = 0;
+  for (int g : G) total += g;
+  // descriptors, workgroup map, packed states
+  std::vector<Inst> insts((size_t)count);
+  std::vector<int> wgmap((size_t)total);
+  std::vector<int32_t> states(bl.states_words, 0);
+  int wg = 0;
+  for (int t = 0; t < count; ++t) {
+    mpts_ctx *c = ctxs[t];
+    st = mpts_pack_state(c, x0 + 3 * t, states.data() + bl.state_off[t]);
+    if (st) return set_err(c0, st, "bad initial state");
+    char *rb = base + bl.region[t];
+    Layout l = layout(c, 0, false, 1);
+    Inst &I = insts[t];
+    memset(&I, 0, sizeof(I));
+    I.L = c->L;
+    I.N = c->N;
+    I.nd = c->nd;
+    I.RS = c->RS;
+    I.WB = c->WB;
+    I.CM = bl.CM;
+    I.G = G[t];
+    I.wg0 = wg;
+    I.mode = MODE_INTEGRATE;
+    I.nsteps = nsteps[t];
+    I.rows = (int32_t *)(rb + l.rows);
+    I.consts = (int32_t *)(rb + l.consts);
+    I.cnorm = (int32_t *)(rb + l.cnorm);
+    I.state = (int32_t *)(base + bl.states) + bl.state_off[t];
+    I.gframes = (long long *)(rb + l.gframes);
+    I.sync = (uint32_t *)(rb + l.sync);
+    for (int j = 0; j < G[t]; ++j) wgmap[wg + j] = t;
+    wg += G[t];
+    hipError_t e = hipMemcpyAsync(rb + l.cnorm, c->cn.data(), c->cn.size() * 4,
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_err(c0, e, "copy constants");
+  }
+  hipError_t e = hipMemcpyAsync(base + bl.states, states.data(), states.size() * 4,
+                                hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_err(c0, e, "copy states");
+  e = hipMemcpyAsync(base + bl.insts, insts.data(), insts.size() * sizeof(Inst),
+                     hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_err(c0, e, "copy descriptors");
+  e = hipMemcpyAsync(base + bl.wgmap, wgmap.data(), wgmap.size() * 4, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_err(c0, e, "copy map");
+  // device work: clear the synchronisation words and frames, run
+  auto device_work = [&](bool cooperative) -> hipError_t {
+    for (int t = 0; t < count; ++t) {
+      mpts_ctx *c = ctxs[t];
+      Layout l = layout(c, 0, false, 1);
+      char *rb = base + bl.region[t];
+      hipError_t e2 = launch_clear(rb + l.sync, SY_WORDS * 4, s);
+      if (e2 != hipSuccess) return e2;
+      if (G[t] > 1) {
+        e2 = launch_clear(rb + l.gframes, (size_t)2 * NFR * c->WB * 8, s);
+        if (e2 != hipSuccess) return e2;
+      }
+    }
+    return launch_run((const Inst *)(base + bl.insts), (const int *)(base + bl.wgmap), total,
+                      bl.CM, bl.lds, s, cooperative);
+  };
+  if (flags & MPTS_GRAPH) {
+    GraphKey key;
+    key.ws = ws;
+    key.ctxs.assign(ctxs, ctxs + count);
+    key.nsteps.assign(nsteps, nsteps + count);
+    key.G = G;
+    hipGraphExec_t exec = graph_lookup(key);
+    if (!exec) {
+      // capture on a private stream (the caller's may be the legacy default
+      // stream, which cannot be captured); the graph is launched on the
+      // caller's stream below
+      e = set_kernel_lds(bl.CM, bl.lds);
+      if (e != hipSuccess) return hip_err(c0, e, "kernel attributes");
+      hipStream_t cap;
+      e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+      if (e != hipSuccess) return hip_err(c0, e, "capture stream");
+      hipStream_t user = s;
+      s = cap;
+      hipGraph_t graph = nullptr;
+      e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+      hipError_t we = hipSuccess;
+      if (e == hipSuccess) {
+        we = device_work(false);
+        e = hipStreamEndCapture(cap, &graph);
+      }
+      s = user;
+      (void)hipStreamDestroy(cap);
+      if (we != hipSuccess) return hip_err(c0, we, "captured launch");
+      if (e != hipSuccess) return hip_err(c0, e, "capture");
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) return hip_err(c0, e, "instantiate graph");
+      graph_store(key, exec);
+    }
+    e = hipGraphLaunch(exec, s);
+    if (e != hipSuccess) return hip_err(c0, e, "graph launch");
+  } else {
+    e = device_work(true);
+    if (e != hipSuccess) return hip_err(c0, e, "launch");
+  }
+  e = hipMemcpyAsync(states.data(), base + bl.states, states.size() * 4, hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return hip_err(c0, e, "copy states out");
+  std::vector<uint32_t> errs((size_t)count, 0u);
+  for (int t = 0; t < count; ++t) {
+    Layout l = layout(ctxs[t], 0, false, 1);
+    e = hipMemcpyAsync(&errs[t], base + bl.region[t] + l.sync + SY_ERROR * 4, 4,
+                       hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_err(c0, e, "read status");
+  }
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_err(c0, e, "synchronize");
+  for (int t = 0; t < count; ++t) {
+    if (errs[t] & 4u) return set_err(c0, MPTS_EHIP, "device synchronisation timed out");
+    if (errs[t] & 3u) return set_err(c0, MPTS_ERANGE, "exact sum outside the device window");
+  }
+  for (int t = 0; t < count; ++t) {
+    st = mpts_unpack_state(ctxs[t], states.data() + bl.state_off[t], x_out + 3 * t);
+    if (st) return st;
+  }
+  return MPTS_OK;
 }
 
 int mpts_grad(mpts_ctx *c, const mpts_bf x0[3], int64_t nsteps, double grad_out[6],

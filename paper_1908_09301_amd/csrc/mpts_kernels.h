@@ -9,10 +9,15 @@ namespace mpts {
 // Bytes of dynamic LDS one workgroup of the forward kernel needs.
 size_t lds_bytes(int L, int N, int RS, int WB, int CM);
 
-// Cooperative launch of the persistent forward kernel over `nwg` workgroups;
-// workgroup w runs trajectory d_insts[d_wg_inst[w]].
+// Launch of the persistent forward kernel over `nwg` workgroups; workgroup w
+// runs trajectory d_insts[d_wg_inst[w]].  `cooperative` asks the runtime to
+// guarantee that all workgroups are resident together; the plain launch
+// (used under graph capture) relies on nwg not exceeding what fits at once.
 hipError_t launch_run(const Inst *d_insts, const int *d_wg_inst, int nwg, int CM, size_t lds,
-                      hipStream_t s);
+                      hipStream_t s, bool cooperative);
+
+// Allow the forward kernel instance for CM the given dynamic LDS size.
+hipError_t set_kernel_lds(int CM, size_t lds);
 
 // Zero `bytes` of device memory with a kernel (usable under graph capture).
 hipError_t launch_clear(void *p, size_t bytes, hipStream_t s);

@@ -347,12 +347,12 @@ __global__ void __launch_bounds__(WGS) k_run(const Inst *__restrict__ insts,
     for (int i = 0; i < N; ++i) {
       if (tid == 0) {
         FrameSrc *fs = cv.fs;
-        fs[0] = FrameSrc{0, i + 1, row_ptr(I, 0, 0), row_ptr(I, 2, 0), nullptr, nullptr, i};
-        fs[1] = FrameSrc{0, i + 1, row_ptr(I, 0, 0), row_ptr(I, 1, 0), nullptr, nullptr, i};
-        fs[2] = FrameSrc{1, 2, I.consts + (size_t)C_SIGMA * RS, row_ptr(I, 1, i),
-                         I.consts + (size_t)C_NSIGMA * RS, row_ptr(I, 0, i), 0};
-        fs[3] = FrameSrc{1, 1, I.consts + (size_t)C_R * RS, row_ptr(I, 0, i), nullptr, nullptr, 0};
-        fs[4] = FrameSrc{1, 1, I.consts + (size_t)C_NB * RS, row_ptr(I, 2, i), nullptr, nullptr, 0};
+        fs[0] = mk_frame1(mk_part(PK_CAUCHY, i + 1, i, row_ptr(I, 0, 0), row_ptr(I, 2, 0)));
+        fs[1] = mk_frame1(mk_part(PK_CAUCHY, i + 1, i, row_ptr(I, 0, 0), row_ptr(I, 1, 0)));
+        fs[2] = mk_frame2(mk_part(PK_ONE, 1, 0, I.consts + (size_t)C_SIGMA * RS, row_ptr(I, 1, i)),
+                          mk_part(PK_ONE, 1, 0, I.consts + (size_t)C_NSIGMA * RS, row_ptr(I, 0, i)));
+        fs[3] = mk_frame1(mk_part(PK_ONE, 1, 0, I.consts + (size_t)C_R * RS, row_ptr(I, 0, i)));
+        fs[4] = mk_frame1(mk_part(PK_ONE, 1, 0, I.consts + (size_t)C_NB * RS, row_ptr(I, 2, i)));
       }
       __syncthreads();
       frame_setup(cv.fs, cv.fd, NFR, nd, RS, cv.red, cv.offs, cv.maxn, err);
@@ -425,7 +425,7 @@ __global__ void __launch_bounds__(WGS) k_run(const Inst *__restrict__ insts,
       for (int i = N - 1; i >= 0; --i) {
         if (tid == 0) {
           for (int c = 0; c < 3; ++c)
-            cv.fs[c] = FrameSrc{1, 1, tau_lds, cv.hrow + (size_t)c * RS, nullptr, nullptr, 0};
+            cv.fs[c] = mk_frame1(mk_part(PK_ONE, 1, 0, tau_lds, cv.hrow + (size_t)c * RS));
           frame_setup_single(cv.fs, cv.fd, 3, nd, cv.offs, cv.maxn);
         }
         __syncthreads();
@@ -477,13 +477,43 @@ static hipError_t launch_cm(const Inst *d_insts, const int *d_wg_inst, int nwg, 
                                     s);
 }
 
+template <int CM>
+static hipError_t launch_cm_plain(const Inst *d_insts, const int *d_wg_inst, int nwg, size_t lds,
+                                  hipStream_t s) {
+  auto kern = k_run<CM>;
+  hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(nwg), dim3(WGS), lds, s, d_insts, d_wg_inst);
+  return hipGetLastError();
+}
+
 hipError_t launch_run(const Inst *d_insts, const int *d_wg_inst, int nwg, int CM, size_t lds,
-                      hipStream_t s) {
+                      hipStream_t s, bool cooperative) {
+  if (cooperative) {
+    switch (CM) {
+      case 4: return launch_cm<4>(d_insts, d_wg_inst, nwg, lds, s);
+      case 8: return launch_cm<8>(d_insts, d_wg_inst, nwg, lds, s);
+      case 16: return launch_cm<16>(d_insts, d_wg_inst, nwg, lds, s);
+      case 32: return launch_cm<32>(d_insts, d_wg_inst, nwg, lds, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (CM) {
-    case 4: return launch_cm<4>(d_insts, d_wg_inst, nwg, lds, s);
-    case 8: return launch_cm<8>(d_insts, d_wg_inst, nwg, lds, s);
-    case 16: return launch_cm<16>(d_insts, d_wg_inst, nwg, lds, s);
-    case 32: return launch_cm<32>(d_insts, d_wg_inst, nwg, lds, s);
+    case 4: return launch_cm_plain<4>(d_insts, d_wg_inst, nwg, lds, s);
+    case 8: return launch_cm_plain<8>(d_insts, d_wg_inst, nwg, lds, s);
+    case 16: return launch_cm_plain<16>(d_insts, d_wg_inst, nwg, lds, s);
+    case 32: return launch_cm_plain<32>(d_insts, d_wg_inst, nwg, lds, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t set_kernel_lds(int CM, size_t lds) {
+  switch (CM) {
+    case 4: return hipFuncSetAttribute((const void *)k_run<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    case 8: return hipFuncSetAttribute((const void *)k_run<8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    case 16: return hipFuncSetAttribute((const void *)k_run<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    case 32: return hipFuncSetAttribute((const void *)k_run<32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     default: return hipErrorInvalidValue;
   }
 }

@@ -92,12 +92,21 @@ __device__ void write_row(const int32_t *nv, int L, int nd, int RS, int32_t *row
 // exactly in 64-bit integers over a share of the terms and adds them into
 // the frame's column array.
 
+// Terms of a frame come in up to three parts; part kinds:
+//   CAUCHY: k = 0..n-1 -> U[idx - k] * V[k]   (rows of stride RS)
+//   CORR:   k = 0..n-1 -> U[idx + k] * V[k]
+//   DOT:    k = 0..n-1 -> U[k] * V[k]
+//   ONE:    one term U * V
+enum { PK_CAUCHY = 0, PK_CORR = 1, PK_DOT = 2, PK_ONE = 3 };
+
+struct FramePart {
+  int kind, n, idx, pad;
+  const int32_t *U, *V;
+};
+
 struct FrameSrc {
-  int kind;            // 0: Cauchy sum_{k=0}^{i} U[i-k] V[k]; 1: explicit list
-  int n;               // number of terms
-  const int32_t *U0, *V0;   // kind 0: row arrays (stride RS); kind 1: term 0
-  const int32_t *U1, *V1;   // kind 1: term 1
-  int i;
+  int nparts, n;  // n = total terms
+  FramePart p[3];
 };
 
 struct FrameD {
@@ -105,15 +114,74 @@ struct FrameD {
   long long cost0;     // first cost unit of this frame
 };
 
+__device__ __forceinline__ void part_term(const FramePart &q, int k, int RS, const int32_t **U,
+                                          const int32_t **V) {
+  switch (q.kind) {
+    case PK_CAUCHY:
+      *U = q.U + (long long)(q.idx - k) * RS;
+      *V = q.V + (long long)k * RS;
+      break;
+    case PK_CORR:
+      *U = q.U + (long long)(q.idx + k) * RS;
+      *V = q.V + (long long)k * RS;
+      break;
+    case PK_DOT:
+      *U = q.U + (long long)k * RS;
+      *V = q.V + (long long)k * RS;
+      break;
+    default:
+      *U = q.U;
+      *V = q.V;
+  }
+}
+
 __device__ __forceinline__ void frame_term(const FrameSrc &f, int k, int RS, const int32_t **U,
                                            const int32_t **V) {
-  if (f.kind == 0) {
-    *U = f.U0 + (long long)(f.i - k) * RS;
-    *V = f.V0 + (long long)k * RS;
+  if (k < f.p[0].n || f.nparts == 1) {
+    part_term(f.p[0], k, RS, U, V);
+  } else if (f.nparts == 2 || k < f.p[0].n + f.p[1].n) {
+    part_term(f.p[1], k - f.p[0].n, RS, U, V);
   } else {
-    *U = k == 0 ? f.U0 : f.U1;
-    *V = k == 0 ? f.V0 : f.V1;
+    part_term(f.p[2], k - f.p[0].n - f.p[1].n, RS, U, V);
   }
+}
+
+__host__ __device__ inline FramePart mk_part(int kind, int n, int idx, const int32_t *U,
+                                             const int32_t *V) {
+  FramePart q;
+  q.kind = kind;
+  q.n = n;
+  q.idx = idx;
+  q.pad = 0;
+  q.U = U;
+  q.V = V;
+  return q;
+}
+
+__host__ __device__ inline FrameSrc mk_frame1(FramePart a) {
+  FrameSrc f;
+  f.nparts = 1;
+  f.n = a.n;
+  f.p[0] = a;
+  f.p[1] = a;
+  f.p[2] = a;
+  return f;
+}
+
+__host__ __device__ inline FrameSrc mk_frame2(FramePart a, FramePart b) {
+  FrameSrc f = mk_frame1(a);
+  f.nparts = 2;
+  f.n = a.n + b.n;
+  f.p[1] = b;
+  return f;
+}
+
+__host__ __device__ inline FrameSrc mk_frame3(FramePart a, FramePart b, FramePart c) {
+  FrameSrc f = mk_frame2(a, b);
+  f.nparts = 3;
+  f.n = a.n + b.n + c.n;
+  f.p[2] = c;
+  return f;
 }
 
 // Tile (mt, nt) of the t-th tile in anti-diagonal order of an MT x NT grid
@@ -245,7 +313,7 @@ __device__ void frame_setup_single(const FrameSrc *fs, FrameD *fd, int nf, int n
   long long c = 0;
   for (int f = 0; f < nf; ++f) {
     FrameD d;
-    const int32_t *U = fs[f].U0, *V = fs[f].V0;
+    const int32_t *U = fs[f].p[0].U, *V = fs[f].p[0].V;
     d.n = 1;
     d.nz = (U[1] != 0 && V[1] != 0) ? 1 : 0;
     d.base = d.nz ? U[0] + V[0] : 0;

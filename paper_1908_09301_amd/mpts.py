@@ -322,7 +322,7 @@ def integrate_batch(problems: Sequence[Lorenz], x0s, nsteps: Sequence[int], flag
     st = _lib.mpts_integrate_batch(hs, n, ins, ns, outs, ctypes.c_void_p(ws.data_ptr()),
                                    ws.numel(), _stream(), flags)
     if st != MPTS_OK:
-        raise MptsError(st)
+        raise MptsError(st, _lib.mpts_last_error(problems[0].handle).decode())
     res = []
     for t, p in enumerate(problems):
         r = []
