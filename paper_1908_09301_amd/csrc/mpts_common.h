@@ -32,13 +32,17 @@ enum { SY_ARRIVE = 0, SY_FLAG = 32, SY_ERROR = 64, SY_WORDS = 96 };
 
 enum { MODE_INTEGRATE = 0, MODE_COEFFS = 1, MODE_ADJOINT = 2 };
 
-inline int digits_per_row(int L) { return (32 * L + DBITS - 1 + DBITS - 1) / DBITS; }
+__host__ __device__ inline int digits_per_row(int L) { return (32 * L + DBITS - 1 + DBITS - 1) / DBITS; }
 inline int row_stride(int nd) { int rs = HDR + RPAD + nd + RPAD + TQ; return (rs + 31) & ~31; }
 // frame width in columns: products of two rows span 2 nd - 1 columns, plus the
 // spread, plus the tile overhang of the last diagonal, plus carries.
 inline int frame_width(int nd) { int w = 2 * nd + SMAX + 2 * TQ + 8; return (w + 31) & ~31; }
 // digits one single-wave big-integer task must hold (combine + division)
 inline int task_digits(int nd) { return 3 * nd + 2 * SMAX + 48; }
+// bytes of the per-term offset table: the frames of one index hold at most
+// 5 (N + 1) terms (forward) or 3 (2N + 2) terms (adjoint), each frame's
+// slice rounded up to 16
+__host__ __device__ inline int max_terms(int N) { return 6 * N + 6 + 5 * 16; }
 
 struct Inst {
   int L, N, nd, RS, WB, CM;  // limbs, order, digits/row, row stride, frame width, chunk max

@@ -310,7 +310,7 @@ int choose_cm(int nd) {
 }
 
 struct Layout {
-  size_t prof, sync, cnorm, state, consts, rows, gframes, coefs, ckpt, inst, wgmap, total;
+  size_t prof, sync, cnorm, state, consts, rows, gframes, coefs, ckpt, adj, inst, wgmap, total;
 };
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -342,6 +342,9 @@ Layout layout(const mpts_ctx *c, long long nsteps, bool ckpt, int nwg) {
   o = al(o + (size_t)kMaxWG * 4);
   l.ckpt = o;
   if (ckpt) o = al(o + (size_t)(nsteps + 1) * 3 * (c->L + 2) * 4);
+  l.adj = o;
+  if (ckpt)
+    o = al(o + ((size_t)6 * c->N * c->RS + (size_t)3 * (c->N + 1) * c->RS + (size_t)6 * (c->L + 2)) * 4);
   l.total = o;
   (void)nwg;
   return l;
@@ -432,7 +435,7 @@ int make_ctx(const char *sigma, const char *R, const char *b, int L, int N, cons
 
 int run_single(mpts_ctx *c, int mode, long long nsteps, const void *x0_dev, void *xout_dev,
                void *ckpt_dev, void *ws, size_t ws_bytes, hipStream_t s, bool x0_on_host,
-               const int32_t *x0_host) {
+               const int32_t *x0_host, void *adj_dev = nullptr) {
   int dst = check_device(c);
   if (dst != MPTS_OK) return dst;
   int G = c->wgs > 0 ? c->wgs : c->cus;
@@ -477,13 +480,17 @@ int run_single(mpts_ctx *c, int mode, long long nsteps, const void *x0_dev, void
   I.ckpt = (int32_t *)ckpt_dev;
   I.gframes = (long long *)(base + l.gframes);
   I.sync = (uint32_t *)(base + l.sync);
+  I.adj = (int32_t *)adj_dev;
   I.prof = phases ? (unsigned long long *)(base + l.prof) : nullptr;
   e = hipMemcpyAsync(base + l.inst, &I, sizeof(I), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_err(c, e, "copy descriptor");
   e = launch_clear(base + l.wgmap, (size_t)G * 4, s);
   if (e != hipSuccess) return hip_err(c, e, "clear");
-  e = launch_run((const Inst *)(base + l.inst), (const int *)(base + l.wgmap), G, c->CM, c->lds, s,
-                 true);
+  if (mode == MODE_ADJOINT)
+    e = launch_adj((const Inst *)(base + l.inst), (const int *)(base + l.wgmap), G, c->CM, c->lds, s);
+  else
+    e = launch_run((const Inst *)(base + l.inst), (const int *)(base + l.wgmap), G, c->CM, c->lds,
+                   s, true);
   if (e != hipSuccess) return hip_err(c, e, "launch");
   if (xout_dev) {
     e = hipMemcpyAsync(xout_dev, base + l.state, sb, hipMemcpyDeviceToDevice, s);
@@ -1050,9 +1057,44 @@ int mpts_integrate_batch(mpts_ctx *const *ctxs, int32_t count, const mpts_bf *x0
 
 int mpts_grad(mpts_ctx *c, const mpts_bf x0[3], int64_t nsteps, double grad_out[6],
               mpts_bf *grad_bf, mpts_bf x_out[3], void *ws, size_t ws_bytes, void *stream) {
-  (void)c; (void)x0; (void)nsteps; (void)grad_out; (void)grad_bf; (void)x_out; (void)ws;
-  (void)ws_bytes; (void)stream;
-  return MPTS_EUNSUPPORTED;
+  if (!c || !x0 || !grad_out || !ws || nsteps < 0) return MPTS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<int32_t> packed((size_t)3 * (c->L + 2));
+  int st = mpts_pack_state(c, x0, packed.data());
+  if (st) return set_err(c, st, "bad initial state");
+  Layout l = layout(c, nsteps, true, 1);
+  if (ws_bytes < l.total) return set_err(c, MPTS_ENOSPC, "workspace too small");
+  char *base = (char *)ws;
+  // forward run keeping every step's state
+  st = run_single(c, MODE_INTEGRATE, nsteps, nullptr, nullptr, base + l.ckpt, ws, ws_bytes, s, true,
+                  packed.data());
+  if (st) return st;
+  st = read_status(c, ws, s);
+  if (st) return st;
+  // reverse sweep (the state buffer is not read in this mode)
+  st = run_single(c, MODE_ADJOINT, nsteps, nullptr, nullptr, base + l.ckpt, ws, ws_bytes, s, true,
+                  packed.data(), base + l.adj);
+  if (st) return st;
+  const size_t nvw = (size_t)c->L + 2;
+  std::vector<int32_t> bars(6 * nvw), fin(3 * nvw);
+  const size_t bar_off =
+      l.adj + ((size_t)6 * c->N * c->RS + (size_t)3 * (c->N + 1) * c->RS) * 4;
+  hipError_t e = hipMemcpyAsync(bars.data(), base + bar_off, bars.size() * 4, hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return hip_err(c, e, "copy gradient");
+  e = hipMemcpyAsync(fin.data(), base + l.ckpt + (size_t)nsteps * 3 * nvw * 4, fin.size() * 4,
+                     hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return hip_err(c, e, "copy final state");
+  st = read_status(c, ws, s);
+  if (st) return st;
+  for (int j = 0; j < 6; ++j) {
+    grad_out[j] = nv_to_double(bars.data() + j * nvw, c->L);
+    if (grad_bf) {
+      st = nv_to_bf(c, bars.data() + j * nvw, &grad_bf[j]);
+      if (st) return st;
+    }
+  }
+  if (x_out) return mpts_unpack_state(c, fin.data(), x_out);
+  return MPTS_OK;
 }
 
 const char *mpts_strerror(int status) {

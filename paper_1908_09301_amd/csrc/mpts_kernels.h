@@ -16,6 +16,10 @@ size_t lds_bytes(int L, int N, int RS, int WB, int CM);
 hipError_t launch_run(const Inst *d_insts, const int *d_wg_inst, int nwg, int CM, size_t lds,
                       hipStream_t s, bool cooperative);
 
+// Cooperative launch of the adjoint kernel (reverse sweep over checkpoints).
+hipError_t launch_adj(const Inst *d_insts, const int *d_wg_inst, int nwg, int CM, size_t lds,
+                      hipStream_t s);
+
 // Allow the forward kernel instance for CM the given dynamic LDS size.
 hipError_t set_kernel_lds(int CM, size_t lds);
 

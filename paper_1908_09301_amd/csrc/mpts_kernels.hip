@@ -173,14 +173,14 @@ __device__ Carve carve(unsigned char *smem, const Inst &I) {
   p += 64 * 4;
   c.span = (int *)p;
   p += 2 * NFR * 4;
-  c.maxn = (I.N + 1 + 15) & ~15;
+  c.maxn = max_terms(I.N);
   c.offs = (int8_t *)p;
   return c;
 }
 
 size_t lds_bytes(int L, int N, int RS, int WB, int CM) {
   const int NV = (L + 2 + 3) & ~3;
-  const int maxn = (N + 1 + 15) & ~15;
+  const int maxn = max_terms(N);
   size_t b = (size_t)NFR * WB * 8 + (size_t)3 * 64 * CM * 8 + (size_t)3 * 64 * CM * 4 +
              (size_t)6 * NV * 4 + (size_t)4 * RS * 4 + sizeof(FrameSrc) * NFR +
              sizeof(FrameD) * (NFR + 1) + 64 * 4 + 2 * NFR * 4 + (size_t)NFR * maxn;
@@ -189,6 +189,20 @@ size_t lds_bytes(int L, int N, int RS, int WB, int CM) {
 
 __device__ __forceinline__ int32_t *row_ptr(const Inst &I, int arr, int idx) {
   return I.rows + ((long long)arr * (I.N + 1) + idx) * I.RS;
+}
+
+// Adjoint rows: u, v, w and their negations (N rows each), the powers of
+// tau times the incoming adjoints (3 x (N+1) rows), and six normalised
+// values: the adjoints of the state and of sigma, R, b.
+enum { A_U = 0, A_V, A_W, A_NU, A_NV, A_NW };
+__device__ __forceinline__ int32_t *adj_row(const Inst &I, int arr, int idx) {
+  return I.adj + ((long long)arr * I.N + idx) * I.RS;
+}
+__device__ __forceinline__ int32_t *q_row(const Inst &I, int c, int idx) {
+  return I.adj + (long long)6 * I.N * I.RS + ((long long)c * (I.N + 1) + idx) * I.RS;
+}
+__device__ __forceinline__ int32_t *bar_ptr(const Inst &I, int j) {
+  return I.adj + (long long)6 * I.N * I.RS + (long long)3 * (I.N + 1) * I.RS + (long long)j * (I.L + 2);
 }
 
 __device__ __forceinline__ void copy_norm(const int32_t *src, int32_t *dst, int L, bool relaxed,
@@ -284,6 +298,167 @@ __device__ void finalize_task(const Inst &I, const Carve &cv, int which, int i,
               64);
 }
 
+// ---------------------------------------------------------------------------
+// Group protocol: one coefficient (or adjoint) index at a time.
+struct GroupSync {
+  uint32_t gen;
+  unsigned long long nbulk;
+};
+
+// Leader: after writing rows that the group will read, publish them.
+// Followers: wait for that publication.
+__device__ void group_publish(const Inst &I, bool leader, GroupSync &gs, uint32_t *err) {
+  const int tid = threadIdx.x;
+  if (leader) {
+    wait_vmem();
+    __syncthreads();
+    ++gs.gen;
+    if (I.G > 1 && tid == 0) st_relaxed(I.sync + SY_FLAG, gs.gen);
+  } else {
+    ++gs.gen;
+    if (tid == 0) spin_until(I.sync + SY_FLAG, gs.gen, err);
+    __syncthreads();
+  }
+}
+
+// Every workgroup of the group: frame descriptors, this workgroup's share
+// of the products into LDS, and (G > 1) the L2-bypassing atomic adds of
+// its columns into the group's global frames.  The leader then waits for
+// every workgroup's adds.  Returns the frames the leader finalises from.
+__device__ const long long *group_bulk(const Inst &I, const Carve &cv, int nf, int rank,
+                                       GroupSync &gs, uint32_t *err) {
+  const int tid = threadIdx.x;
+  const int G = I.G, WB = I.WB;
+  frame_setup(cv.fs, cv.fd, nf, I.nd, I.RS, cv.red, cv.offs, cv.maxn, err);
+  frames_accumulate(cv.fs, cv.fd, nf, I.nd, I.RS, WB, cv.lf, rank, G, cv.span, cv.offs, cv.maxn);
+  __syncthreads();
+  ++gs.nbulk;
+  long long *gf = I.gframes + (size_t)(gs.nbulk & 1) * NFR * WB;
+  if (G == 1) return cv.lf;
+  for (int f = 0; f < nf; ++f) {
+    int c0 = cv.span[2 * f], c1 = cv.span[2 * f + 1];
+    for (int c = c0 + tid; c < c1; c += WGS) {
+      long long v = cv.lf[(size_t)f * WB + c];
+      if (v != 0) {
+        __hip_atomic_fetch_add((unsigned long long *)(gf + (size_t)f * WB + c),
+                               (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        cv.lf[(size_t)f * WB + c] = 0;
+      }
+    }
+  }
+  wait_vmem();
+  __syncthreads();
+  if (tid == 0)
+    __hip_atomic_fetch_add(I.sync + SY_ARRIVE, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (rank == 0) {
+    if (tid == 0) spin_until(I.sync + SY_ARRIVE, (uint32_t)(G * gs.nbulk), err);
+    __syncthreads();
+  }
+  return gf;
+}
+
+// Leader: clear the frames it finalised from, then publish its new rows.
+// Followers: wait for the publication.
+__device__ void group_release(const Inst &I, const Carve &cv, int nf, bool leader,
+                              const long long *frames, GroupSync &gs, uint32_t *err) {
+  const int tid = threadIdx.x;
+  if (leader) {
+    __syncthreads();
+    for (int f = 0; f < nf; ++f) {
+      int nc = cv.fd[f].nz ? frame_cols(cv.fd[f], I.nd) : 0;
+      long long *fr = const_cast<long long *>(frames) + (size_t)f * I.WB;
+      for (int c = tid; c < nc; c += WGS) {
+        if (I.G > 1) st_relaxed(fr + c, 0LL);
+        else fr[c] = 0;
+      }
+    }
+  }
+  group_publish(I, leader, gs, err);
+}
+
+// Rows 0 of the three coefficient arrays from a normalised state, published
+// to the group; then, once per step, drop cached copies of rows that are
+// about to be rewritten.
+__device__ void start_step(const Inst &I, bool leader, const int32_t *state, GroupSync &gs,
+                           uint32_t *err) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  if (leader && wave < 3)
+    write_row(state + (size_t)wave * (I.L + 2), I.L, I.nd, I.RS, row_ptr(I, wave, 0), I.G > 1,
+              lane, 64);
+  group_publish(I, leader, gs, err);
+  if (I.G > 1) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __syncthreads();
+  }
+}
+
+// The Taylor coefficients 1..N of one step (equation (3)), rows 0 given.
+template <int CM>
+__device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, GroupSync &gs,
+                                     uint32_t *err) {
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const bool leader = rank == 0;
+  const int RS = I.RS;
+  for (int i = 0; i < I.N; ++i) {
+    if (tid == 0) {
+      FrameSrc *fs = cv.fs;
+      fs[0] = mk_frame1(mk_part(PK_CAUCHY, i + 1, i, row_ptr(I, 0, 0), row_ptr(I, 2, 0)));
+      fs[1] = mk_frame1(mk_part(PK_CAUCHY, i + 1, i, row_ptr(I, 0, 0), row_ptr(I, 1, 0)));
+      fs[2] = mk_frame2(mk_part(PK_ONE, 1, 0, I.consts + (size_t)C_SIGMA * RS, row_ptr(I, 1, i)),
+                        mk_part(PK_ONE, 1, 0, I.consts + (size_t)C_NSIGMA * RS, row_ptr(I, 0, i)));
+      fs[3] = mk_frame1(mk_part(PK_ONE, 1, 0, I.consts + (size_t)C_R * RS, row_ptr(I, 0, i)));
+      fs[4] = mk_frame1(mk_part(PK_ONE, 1, 0, I.consts + (size_t)C_NB * RS, row_ptr(I, 2, i)));
+    }
+    __syncthreads();
+    const long long *frames = group_bulk(I, cv, NFR, rank, gs, err);
+    if (leader && wave < 3) finalize_task<CM>(I, cv, wave, i, frames, I.G > 1, err);
+    group_release(I, cv, NFR, leader, frames, gs, err);
+  }
+}
+
+// Three single-workgroup chains at once on the leader: h_c <- round(tau h_c
+// + addend_c(i)) for `count` iterations.  h_c starts as the row start_c (an
+// LDS row in cv.hrow[c] must already hold it).  Used for the Horner sums of
+// equation (2) (addend: coefficient rows) and for the adjoint's powers of tau
+// (no addend; each result row is also stored to out rows).
+template <int CM>
+__device__ void tau_chains(const Inst &I, const Carve &cv, int count, int mode, uint32_t *err) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int L = I.L, nd = I.nd, RS = I.RS, WB = I.WB, N = I.N;
+  const int32_t *tau_lds = cv.hrow + (size_t)3 * RS;
+  for (int it = 0; it < count; ++it) {
+    if (tid == 0) {
+      for (int c = 0; c < 3; ++c)
+        cv.fs[c] = mk_frame1(mk_part(PK_ONE, 1, 0, tau_lds, cv.hrow + (size_t)c * RS));
+      frame_setup_single(cv.fs, cv.fd, 3, nd, cv.offs, cv.maxn);
+    }
+    __syncthreads();
+    frames_accumulate(cv.fs, cv.fd, 3, nd, RS, WB, cv.lf, 0, 1, cv.span, cv.offs, cv.maxn);
+    __syncthreads();
+    if (wave < 3) {
+      int32_t *dig = (int32_t *)(cv.tcols + (size_t)wave * 64 * I.CM);
+      int32_t *h = cv.tnorm + (size_t)wave * 2 * cv.NV;
+      Addend ad;
+      int nad = 0;
+      if (mode == 0) {  // Horner: i = N-1-it
+        ad = Addend{row_ptr(I, wave, N - 1 - it), 1, 1};
+        nad = 1;
+      }
+      int C;
+      long long dexp;
+      int sgn = combine_resolve<CM>(cv.lf + (size_t)wave * WB, false, &cv.fd[wave], nd, L, &ad,
+                                    nad, dig, &C, &dexp, err);
+      bool ok = wave_round(dig, C, sgn, dexp, false, L, h);
+      if (!ok && lane == 0) atomicOr(err, 2u);
+      write_row(h, L, nd, RS, cv.hrow + (size_t)wave * RS, false, lane, 64);
+      if (mode == 1) write_row(h, L, nd, RS, q_row(I, wave, it + 1), I.G > 1, lane, 64);
+      int nc = cv.fd[wave].nz ? frame_cols(cv.fd[wave], nd) : 0;
+      for (int c = lane; c < nc; c += 64) cv.lf[(size_t)wave * WB + c] = 0;
+    }
+    __syncthreads();
+  }
+}
+
 template <int CM>
 __global__ void __launch_bounds__(WGS) k_run(const Inst *__restrict__ insts,
                                              const int *__restrict__ wg_inst) {
@@ -294,14 +469,9 @@ __global__ void __launch_bounds__(WGS) k_run(const Inst *__restrict__ insts,
   const bool leader = rank == 0;
   const int L = I.L, N = I.N, nd = I.nd, RS = I.RS, WB = I.WB;
   uint32_t *err = I.sync + SY_ERROR;
-  uint32_t *flag = I.sync + SY_FLAG;
-  uint32_t *arrive = I.sync + SY_ARRIVE;
   Carve cv = carve(smem, I);
   for (int j = tid; j < NFR * WB; j += WGS) cv.lf[j] = 0;
-  const int32_t *tau_row = I.consts + (size_t)C_TAU * RS;
-  uint32_t gen = 0;
-  unsigned long long nbulk = 0;
-  // phase timers (thread 0 of the leader and of workgroup 1)
+  GroupSync gs{0u, 0ull};
   const bool timed = I.prof != nullptr && tid == 0 && (rank == 0 || rank == 1);
   unsigned long long *prof = timed ? I.prof + (rank == 0 ? 0 : PH_NPHASE) : nullptr;
   unsigned long long tp = timed ? wall_clock64() : 0;
@@ -320,133 +490,24 @@ __global__ void __launch_bounds__(WGS) k_run(const Inst *__restrict__ insts,
   __syncthreads();
 
   for (long long step = 0; step < I.nsteps; ++step) {
-    // rows 0 of the three coefficient arrays are the current state
-    if (leader) {
-      if (wave < 3) {
-        const int32_t *sv = I.state + (size_t)wave * (L + 2);
-        write_row(sv, L, nd, RS, row_ptr(I, wave, 0), G > 1, lane, 64);
-        if (step == 0 && I.ckpt) copy_norm(sv, I.ckpt + (size_t)wave * (L + 2), L, false, lane, 64);
-        if (I.coefs) copy_norm(sv, I.coefs + (size_t)wave * (N + 1) * (L + 2), L, false, lane, 64);
-      }
-      wait_vmem();
-      __syncthreads();
-      ++gen;
-      if (G > 1 && tid == 0) st_relaxed(flag, gen);
-    } else {
-      ++gen;
-      if (tid == 0) spin_until(flag, gen, err);
-      __syncthreads();
+    if (leader && wave < 3) {
+      const int32_t *sv = I.state + (size_t)wave * (L + 2);
+      if (step == 0 && I.ckpt) copy_norm(sv, I.ckpt + (size_t)wave * (L + 2), L, false, lane, 64);
+      if (I.coefs) copy_norm(sv, I.coefs + (size_t)wave * (N + 1) * (L + 2), L, false, lane, 64);
     }
-    if (G > 1) {
-      // rows are rewritten every step: drop cached copies once per step
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      __syncthreads();
-    }
+    start_step(I, leader, I.state, gs, err);
     mark(PH_STEP0);
-
-    for (int i = 0; i < N; ++i) {
-      if (tid == 0) {
-        FrameSrc *fs = cv.fs;
-        fs[0] = mk_frame1(mk_part(PK_CAUCHY, i + 1, i, row_ptr(I, 0, 0), row_ptr(I, 2, 0)));
-        fs[1] = mk_frame1(mk_part(PK_CAUCHY, i + 1, i, row_ptr(I, 0, 0), row_ptr(I, 1, 0)));
-        fs[2] = mk_frame2(mk_part(PK_ONE, 1, 0, I.consts + (size_t)C_SIGMA * RS, row_ptr(I, 1, i)),
-                          mk_part(PK_ONE, 1, 0, I.consts + (size_t)C_NSIGMA * RS, row_ptr(I, 0, i)));
-        fs[3] = mk_frame1(mk_part(PK_ONE, 1, 0, I.consts + (size_t)C_R * RS, row_ptr(I, 0, i)));
-        fs[4] = mk_frame1(mk_part(PK_ONE, 1, 0, I.consts + (size_t)C_NB * RS, row_ptr(I, 2, i)));
-      }
-      __syncthreads();
-      frame_setup(cv.fs, cv.fd, NFR, nd, RS, cv.red, cv.offs, cv.maxn, err);
-      mark(PH_SETUP);
-      frames_accumulate(cv.fs, cv.fd, NFR, nd, RS, WB, cv.lf, rank, G, cv.span, cv.offs, cv.maxn);
-      __syncthreads();
-      mark(PH_ACCUM);
-      ++nbulk;
-      long long *gf = I.gframes + (size_t)(nbulk & 1) * NFR * WB;
-      if (G > 1) {
-        for (int f = 0; f < NFR; ++f) {
-          int c0 = cv.span[2 * f], c1 = cv.span[2 * f + 1];
-          for (int c = c0 + tid; c < c1; c += WGS) {
-            long long v = cv.lf[(size_t)f * WB + c];
-            if (v != 0) {
-              __hip_atomic_fetch_add((unsigned long long *)(gf + (size_t)f * WB + c),
-                                     (unsigned long long)v, __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT);
-              cv.lf[(size_t)f * WB + c] = 0;
-            }
-          }
-        }
-        wait_vmem();
-        __syncthreads();
-        if (tid == 0)
-          __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      mark(PH_FLUSH);
-      if (leader) {
-        if (G > 1) {
-          if (tid == 0) spin_until(arrive, (uint32_t)(G * nbulk), err);
-          __syncthreads();
-        }
-        mark(PH_WAIT);
-        const long long *frames = G > 1 ? gf : cv.lf;
-        if (wave < 3) finalize_task<(CM)>(I, cv, wave, i, frames, G > 1, err);
-        __syncthreads();
-        mark(PH_FINAL);
-        // clear the frames for their next use
-        for (int f = 0; f < NFR; ++f) {
-          int nc = cv.fd[f].nz ? frame_cols(cv.fd[f], nd) : 0;
-          for (int c = tid; c < nc; c += WGS) {
-            if (G > 1) st_relaxed(gf + (size_t)f * WB + c, 0LL);
-            else cv.lf[(size_t)f * WB + c] = 0;
-          }
-        }
-        wait_vmem();
-        __syncthreads();
-        ++gen;
-        if (G > 1 && tid == 0) st_relaxed(flag, gen);
-        mark(PH_CLEAR);
-      } else {
-        ++gen;
-        if (tid == 0) spin_until(flag, gen, err);
-        __syncthreads();
-        mark(PH_WAIT);
-      }
-    }
+    forward_coefficients<CM>(I, cv, rank, gs, err);
+    mark(PH_ACCUM);
     if (I.mode == MODE_COEFFS) break;
-
     // Horner: h = c_N; h <- round(h tau + c_i), i = N-1..0, three chains at once
     if (leader) {
-      // LDS copies of c_N (the three Horner accumulators) and of the tau row
       for (int j = tid; j < 4 * RS; j += WGS) {
         int c = j / RS, w = j - c * RS;
-        cv.hrow[j] = c < 3 ? row_ptr(I, c, N)[w] : tau_row[w];
+        cv.hrow[j] = c < 3 ? row_ptr(I, c, N)[w] : (I.consts + (size_t)C_TAU * RS)[w];
       }
-      const int32_t *tau_lds = cv.hrow + (size_t)3 * RS;
       __syncthreads();
-      for (int i = N - 1; i >= 0; --i) {
-        if (tid == 0) {
-          for (int c = 0; c < 3; ++c)
-            cv.fs[c] = mk_frame1(mk_part(PK_ONE, 1, 0, tau_lds, cv.hrow + (size_t)c * RS));
-          frame_setup_single(cv.fs, cv.fd, 3, nd, cv.offs, cv.maxn);
-        }
-        __syncthreads();
-        frames_accumulate(cv.fs, cv.fd, 3, nd, RS, WB, cv.lf, 0, 1, cv.span, cv.offs, cv.maxn);
-        __syncthreads();
-        if (wave < 3) {
-          long long *cols = cv.tcols + (size_t)wave * 64 * I.CM;
-          int32_t *h = cv.tnorm + (size_t)wave * 2 * cv.NV;
-          Addend ad = Addend{row_ptr(I, wave, i), 1, 1};
-          int C;
-          long long dexp;
-          int sgn = combine_resolve<CM>(cv.lf + (size_t)wave * WB, false, &cv.fd[wave], nd, L, &ad,
-                                        1, (int32_t *)cols, &C, &dexp, err);
-          bool ok = wave_round((int32_t *)cols, C, sgn, dexp, false, L, h);
-          if (!ok && lane == 0) atomicOr(err, 2u);
-          write_row(h, L, nd, RS, cv.hrow + (size_t)wave * RS, false, lane, 64);
-          int nc = cv.fd[wave].nz ? frame_cols(cv.fd[wave], nd) : 0;
-          for (int c = lane; c < nc; c += 64) cv.lf[(size_t)wave * WB + c] = 0;
-        }
-        __syncthreads();
-      }
+      tau_chains<CM>(I, cv, N, 0, err);
       if (wave < 3) {
         const int32_t *h = cv.tnorm + (size_t)wave * 2 * cv.NV;
         copy_norm(h, I.state + (size_t)wave * (L + 2), L, false, lane, 64);
@@ -456,6 +517,144 @@ __global__ void __launch_bounds__(WGS) k_run(const Inst *__restrict__ insts,
       __syncthreads();
       mark(PH_HORNER);
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint: reverse sweep over the steps of a checkpointed forward run.
+//
+// For step n (from the last to the first), with incoming adjoints X, Y, Z of
+// the step's end state, the coefficients a, b, g are recomputed from the
+// checkpoint (the same code as the forward run, hence the same bits), the
+// powers q^c_i = round(q^c_{i-1} tau) of each adjoint are formed (the
+// derivative of the Horner sum of equation (2) with respect to c_i is
+// tau^i), and the recursion of equation (3) is differentiated backwards:
+// for m = N..0
+//   abar_m = round(qx_m + sum_{j=m}^{N-1} (-v_j g_{j-m} + w_j b_{j-m}) - sigma u_m + R v_m)
+//   bbar_m = round(qy_m + sum_{j=m}^{N-1} w_j a_{j-m} + sigma u_m - v_m)
+//   gbar_m = round(qz_m - sum_{j=m}^{N-1} v_j a_{j-m} - b w_m)
+//   u_{m-1} = round(abar_m / m), v_{m-1} = round(bbar_m / m), w_{m-1} = round(gbar_m / m)
+// (terms with u_m, v_m, w_m only for m < N).  The gathers are correlation
+// frames over the stored rows u, v, w and their negations nu, nv, nw.  The
+// parameter derivatives of the step are the dot products
+//   dsigma = sum u_i b_i + sum nu_i a_i, dR = sum v_i a_i, db = sum nw_i g_i,
+// each added into its running adjoint with one rounding.
+template <int CM>
+__global__ void __launch_bounds__(WGS) k_adj(const Inst *__restrict__ insts,
+                                             const int *__restrict__ wg_inst) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const Inst I = insts[wg_inst[blockIdx.x]];
+  const int rank = blockIdx.x - I.wg0, G = I.G;
+  const bool leader = rank == 0;
+  const int L = I.L, N = I.N, nd = I.nd, RS = I.RS, WB = I.WB;
+  uint32_t *err = I.sync + SY_ERROR;
+  Carve cv = carve(smem, I);
+  for (int j = tid; j < NFR * WB; j += WGS) cv.lf[j] = 0;
+  GroupSync gs{0u, 0ull};
+  const bool rel = G > 1;
+  if (leader) {
+    for (int c = wave; c < NCONST; c += 4)
+      write_row(I.cnorm + (size_t)c * (L + 2), L, nd, RS, I.consts + (size_t)c * RS, rel, lane, 64);
+    // seed: the adjoint of ||x(T)||^2 is 2 x(T) (exact); parameter adjoints 0
+    if (wave < 3) {
+      const int32_t *xT = I.ckpt + ((size_t)I.nsteps * 3 + wave) * (L + 2);
+      int32_t *b = bar_ptr(I, wave);
+      for (int j = lane; j < L + 2; j += 64) b[j] = (j == 1 && xT[0] != 0) ? xT[1] + 1 : xT[j];
+      int32_t *pb = bar_ptr(I, 3 + wave);
+      for (int j = lane; j < L + 2; j += 64) pb[j] = 0;
+    }
+  }
+  __syncthreads();
+  const int32_t *cs = I.consts;
+  for (long long n = I.nsteps - 1; n >= 0; --n) {
+    // 1. the step's coefficients from its checkpoint
+    start_step(I, leader, I.ckpt + (size_t)n * 3 * (L + 2), gs, err);
+    forward_coefficients<CM>(I, cv, rank, gs, err);
+    // 2. q^c_0 = incoming adjoint, q^c_i = round(q^c_{i-1} tau)
+    if (leader) {
+      if (wave < 3) {
+        write_row(bar_ptr(I, wave), L, nd, RS, q_row(I, wave, 0), rel, lane, 64);
+        write_row(bar_ptr(I, wave), L, nd, RS, cv.hrow + (size_t)wave * RS, false, lane, 64);
+      } else {
+        for (int j = lane; j < RS; j += 64) cv.hrow[(size_t)3 * RS + j] = cs[(size_t)C_TAU * RS + j];
+      }
+      __syncthreads();
+      tau_chains<CM>(I, cv, N, 1, err);
+    }
+    group_publish(I, leader, gs, err);
+    // 3. reverse sweep over the coefficient index
+    for (int m = N; m >= 0; --m) {
+      if (tid == 0) {
+        const int k = N - m;          // terms of each gather
+        const int one = m < N ? 1 : 0;
+        const int mi = m < N ? m : 0;
+        FrameSrc *fs = cv.fs;
+        fs[0] = mk_frame4(mk_part(PK_CORR, k, m, adj_row(I, A_NV, 0), row_ptr(I, 2, 0)),
+                          mk_part(PK_CORR, k, m, adj_row(I, A_W, 0), row_ptr(I, 1, 0)),
+                          mk_part(PK_ONE, one, 0, cs + (size_t)C_NSIGMA * RS, adj_row(I, A_U, mi)),
+                          mk_part(PK_ONE, one, 0, cs + (size_t)C_R * RS, adj_row(I, A_V, mi)));
+        fs[1] = mk_frame2(mk_part(PK_CORR, k, m, adj_row(I, A_W, 0), row_ptr(I, 0, 0)),
+                          mk_part(PK_ONE, one, 0, cs + (size_t)C_SIGMA * RS, adj_row(I, A_U, mi)));
+        fs[2] = mk_frame2(mk_part(PK_CORR, k, m, adj_row(I, A_NV, 0), row_ptr(I, 0, 0)),
+                          mk_part(PK_ONE, one, 0, cs + (size_t)C_NB * RS, adj_row(I, A_W, mi)));
+      }
+      __syncthreads();
+      const long long *frames = group_bulk(I, cv, 3, rank, gs, err);
+      if (leader && wave < 3) {
+        int32_t *dig = (int32_t *)(cv.tcols + (size_t)wave * 64 * I.CM);
+        int32_t *q = cv.tq + (size_t)wave * 64 * I.CM;
+        int32_t *res = cv.tnorm + (size_t)wave * 2 * cv.NV;
+        int32_t *out = res + cv.NV;
+        Addend ad[2];
+        int nad = 1;
+        ad[0] = Addend{q_row(I, wave, m), 1, 1};
+        if (wave == 1 && m < N) {
+          ad[1] = Addend{adj_row(I, A_NV, m), 1, 1};
+          nad = 2;
+        }
+        int C;
+        long long dexp;
+        int sgn = combine_resolve<CM>(frames + (size_t)wave * WB, rel, &cv.fd[wave], nd, L, ad, nad,
+                                      dig, &C, &dexp, err);
+        bool ok = wave_round(dig, C, sgn, dexp, false, L, res);
+        if (m > 0) {
+          Addend a1 = Addend{res, 0, 1};
+          sgn = combine_resolve<CM>(nullptr, false, nullptr, nd, L, &a1, 1, dig, &C, &dexp, err);
+          ok &= wave_div_round<CM>(dig, C, sgn, dexp, m, L, nd, q, out);
+          // wave 0 -> u, 1 -> v, 2 -> w, with their negations
+          write_row(out, L, nd, RS, adj_row(I, A_U + wave, m - 1), rel, lane, 64);
+          write_row(out, L, nd, RS, adj_row(I, A_NU + wave, m - 1), rel, lane, 64, true);
+        } else {
+          copy_norm(res, bar_ptr(I, wave), L, false, lane, 64);
+        }
+        if (!ok && lane == 0) atomicOr(err, 2u);
+      }
+      group_release(I, cv, 3, leader, frames, gs, err);
+    }
+    // 4. parameter derivatives of this step, one rounded add each
+    if (tid == 0) {
+      FrameSrc *fs = cv.fs;
+      fs[0] = mk_frame2(mk_part(PK_DOT, N, 0, adj_row(I, A_U, 0), row_ptr(I, 1, 0)),
+                        mk_part(PK_DOT, N, 0, adj_row(I, A_NU, 0), row_ptr(I, 0, 0)));
+      fs[1] = mk_frame1(mk_part(PK_DOT, N, 0, adj_row(I, A_V, 0), row_ptr(I, 0, 0)));
+      fs[2] = mk_frame1(mk_part(PK_DOT, N, 0, adj_row(I, A_NW, 0), row_ptr(I, 2, 0)));
+    }
+    __syncthreads();
+    const long long *frames = group_bulk(I, cv, 3, rank, gs, err);
+    if (leader && wave < 3) {
+      int32_t *dig = (int32_t *)(cv.tcols + (size_t)wave * 64 * I.CM);
+      int32_t *res = cv.tnorm + (size_t)wave * 2 * cv.NV;
+      Addend ad = Addend{bar_ptr(I, 3 + wave), 0, 1};
+      int C;
+      long long dexp;
+      int sgn = combine_resolve<CM>(frames + (size_t)wave * WB, rel, &cv.fd[wave], nd, L, &ad, 1,
+                                    dig, &C, &dexp, err);
+      bool ok = wave_round(dig, C, sgn, dexp, false, L, res);
+      if (!ok && lane == 0) atomicOr(err, 2u);
+      copy_norm(res, bar_ptr(I, 3 + wave), L, false, lane, 64);
+    }
+    group_release(I, cv, 3, leader, frames, gs, err);
   }
 }
 
@@ -504,6 +703,29 @@ hipError_t launch_run(const Inst *d_insts, const int *d_wg_inst, int nwg, int CM
     case 8: return launch_cm_plain<8>(d_insts, d_wg_inst, nwg, lds, s);
     case 16: return launch_cm_plain<16>(d_insts, d_wg_inst, nwg, lds, s);
     case 32: return launch_cm_plain<32>(d_insts, d_wg_inst, nwg, lds, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int CM>
+static hipError_t launch_adj_cm(const Inst *d_insts, const int *d_wg_inst, int nwg, size_t lds,
+                                hipStream_t s) {
+  auto kern = k_adj<CM>;
+  hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  void *args[] = {(void *)&d_insts, (void *)&d_wg_inst};
+  return hipLaunchCooperativeKernel((const void *)kern, dim3(nwg), dim3(WGS), args, (unsigned)lds,
+                                    s);
+}
+
+hipError_t launch_adj(const Inst *d_insts, const int *d_wg_inst, int nwg, int CM, size_t lds,
+                      hipStream_t s) {
+  switch (CM) {
+    case 4: return launch_adj_cm<4>(d_insts, d_wg_inst, nwg, lds, s);
+    case 8: return launch_adj_cm<8>(d_insts, d_wg_inst, nwg, lds, s);
+    case 16: return launch_adj_cm<16>(d_insts, d_wg_inst, nwg, lds, s);
+    case 32: return launch_adj_cm<32>(d_insts, d_wg_inst, nwg, lds, s);
     default: return hipErrorInvalidValue;
   }
 }

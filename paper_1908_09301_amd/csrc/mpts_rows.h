@@ -61,8 +61,8 @@ __device__ __forceinline__ uint32_t mant_bits28(const int32_t *M, int L, long lo
 // and zero padding included.  `relaxed` selects L2-bypassing stores (for
 // rows that other workgroups read).
 __device__ void write_row(const int32_t *nv, int L, int nd, int RS, int32_t *row, bool relaxed,
-                          int tid, int nthr) {
-  int s = nv[0];
+                          int tid, int nthr, bool negate = false) {
+  int s = negate ? -nv[0] : nv[0];
   long long E = nv[1];
   long long sh;
   int e = floordiv28(E, &sh);
@@ -106,12 +106,12 @@ struct FramePart {
 
 struct FrameSrc {
   int nparts, n;  // n = total terms
-  FramePart p[3];
+  FramePart p[4];
 };
 
 struct FrameD {
-  int n, base, S, NT, nz, pad;
-  long long cost0;     // first cost unit of this frame
+  int n, base, S, NT, nz, obase;  // obase: first entry of this frame's offset slice
+  long long cost0;                // first cost unit of this frame
 };
 
 __device__ __forceinline__ void part_term(const FramePart &q, int k, int RS, const int32_t **U,
@@ -137,13 +137,12 @@ __device__ __forceinline__ void part_term(const FramePart &q, int k, int RS, con
 
 __device__ __forceinline__ void frame_term(const FrameSrc &f, int k, int RS, const int32_t **U,
                                            const int32_t **V) {
-  if (k < f.p[0].n || f.nparts == 1) {
-    part_term(f.p[0], k, RS, U, V);
-  } else if (f.nparts == 2 || k < f.p[0].n + f.p[1].n) {
-    part_term(f.p[1], k - f.p[0].n, RS, U, V);
-  } else {
-    part_term(f.p[2], k - f.p[0].n - f.p[1].n, RS, U, V);
+  int j = 0;
+  while (j + 1 < f.nparts && k >= f.p[j].n) {
+    k -= f.p[j].n;
+    ++j;
   }
+  part_term(f.p[j], k, RS, U, V);
 }
 
 __host__ __device__ inline FramePart mk_part(int kind, int n, int idx, const int32_t *U,
@@ -165,6 +164,7 @@ __host__ __device__ inline FrameSrc mk_frame1(FramePart a) {
   f.p[0] = a;
   f.p[1] = a;
   f.p[2] = a;
+  f.p[3] = a;
   return f;
 }
 
@@ -181,6 +181,14 @@ __host__ __device__ inline FrameSrc mk_frame3(FramePart a, FramePart b, FramePar
   f.nparts = 3;
   f.n = a.n + b.n + c.n;
   f.p[2] = c;
+  return f;
+}
+
+__host__ __device__ inline FrameSrc mk_frame4(FramePart a, FramePart b, FramePart c, FramePart d) {
+  FrameSrc f = mk_frame3(a, b, c);
+  f.nparts = 4;
+  f.n = a.n + b.n + c.n + d.n;
+  f.p[3] = d;
   return f;
 }
 
@@ -225,7 +233,7 @@ __device__ __forceinline__ void tile_normalize(long long (&acc)[16]) {
 
 // Per-workgroup frame setup: exponent base and spread of each frame's
 // nonzero terms (one workgroup reduction for all frames), and the table of
-// per-term digit offsets offs[f * maxn + k] (0 for zero terms, whose rows
+// per-term digit offsets offs[obase_f + k] (0 for zero terms, whose rows
 // are all-zero digits).  Every thread of the workgroup calls this.
 // red: 4 waves x 2 NFR ints.
 __device__ void frame_setup(const FrameSrc *fs, FrameD *fd, int nf, int nd, int RS, int *red,
@@ -277,20 +285,29 @@ __device__ void frame_setup(const FrameSrc *fs, FrameD *fd, int nf, int nd, int 
     }
     d.S = S;
     d.NT = (nd + S + TQ - 1) / TQ;
-    d.pad = MT;
+    d.obase = 0;
     fd[f] = d;
   }
   __syncthreads();
   if (tid == 0) {
     long long c = 0;
+    int ob = 0;
     for (int f = 0; f < nf; ++f) {
       fd[f].cost0 = c;
       if (fd[f].nz) c += (long long)MT * fd[f].NT * fd[f].n;
+      fd[f].obase = ob;
+      ob += (fs[f].n + 15) & ~15;
     }
     fd[nf].cost0 = c;
+    if (ob > maxn) {  // cannot happen for the frames built here; never write past the table
+      atomicOr(err, 1u);
+      for (int f = 0; f <= nf; ++f) fd[f].cost0 = 0;
+    }
   }
+  __syncthreads();
   for (int f = 0; f < nf; ++f) {
     const int base = fd[f].base, S = fd[f].S;
+    if (fd[f].obase + fs[f].n > maxn) continue;
     for (int k = tid; k < fs[f].n; k += WGS) {
       const int32_t *U, *V;
       frame_term(fs[f], k, RS, &U, &V);
@@ -299,7 +316,7 @@ __device__ void frame_setup(const FrameSrc *fs, FrameD *fd, int nf, int nd, int 
         off = U[0] + V[0] - base;
         if (off < 0 || off > S) off = 0;  // only after a spread error (already flagged)
       }
-      offs[f * maxn + k] = (int8_t)off;
+      offs[fd[f].obase + k] = (int8_t)off;
     }
   }
   __syncthreads();
@@ -319,11 +336,11 @@ __device__ void frame_setup_single(const FrameSrc *fs, FrameD *fd, int nf, int n
     d.base = d.nz ? U[0] + V[0] : 0;
     d.S = 0;
     d.NT = MT;
-    d.pad = MT;
+    d.obase = 16 * f;
     d.cost0 = c;
     if (d.nz) c += (long long)MT * MT;
     fd[f] = d;
-    offs[f * maxn] = 0;
+    offs[16 * f] = 0;
   }
   fd[nf].cost0 = c;
 }
@@ -441,17 +458,18 @@ __device__ void frames_accumulate(const FrameSrc *fs, const FrameD *fd, int nf, 
       cur_d = d;
       since = 0;
     }
-    const int8_t *of = offs + f * maxn;
+    const int8_t *of = offs + fd[f].obase;
+    const int Sf = fd[f].S;
     const FrameSrc src = fs[f];
     int32_t ua[TQ], va[TQ], ub[TQ], vb[TQ];
     const int32_t *U, *V;
     frame_term(src, k0, RS, &U, &V);
-    tile_load(ua, va, U, V, mt, nt, of[k0]);
+    tile_load(ua, va, U, V, mt, nt, min(max((int)of[k0], 0), Sf));
     int k = k0;
     while (k < k1) {
       if (k + 1 < k1) {
         frame_term(src, k + 1, RS, &U, &V);
-        tile_load(ub, vb, U, V, mt, nt, of[k + 1]);
+        tile_load(ub, vb, U, V, mt, nt, min(max((int)of[k + 1], 0), Sf));
       }
       tile_fma(acc, ua, va);
       if (++since == FLUSH_TERMS) {
@@ -462,7 +480,7 @@ __device__ void frames_accumulate(const FrameSrc *fs, const FrameD *fd, int nf, 
       if (k >= k1) break;
       if (k + 1 < k1) {
         frame_term(src, k + 1, RS, &U, &V);
-        tile_load(ua, va, U, V, mt, nt, of[k + 1]);
+        tile_load(ua, va, U, V, mt, nt, min(max((int)of[k + 1], 0), Sf));
       }
       tile_fma(acc, ub, vb);
       if (++since == FLUSH_TERMS) {

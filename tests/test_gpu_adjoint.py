@@ -1,0 +1,59 @@
+"""The hand-written adjoint (reverse sweep over checkpoints) against the
+oracle's adjoint, bit for bit, and against central differences of GPU
+forward runs (GPU)."""
+import sys
+from fractions import Fraction
+
+import pytest
+
+from oracle import lorenz as lz
+from oracle.adjoint import grad_sqnorm
+from oracle.bigfloat import to_double
+from workloads import BENCH_X0, box_state, double_strings
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("L,N,nsteps,wgs", [(4, 6, 3, 0), (4, 6, 3, 1), (12, 40, 5, 0),
+                                            (12, 40, 5, 7), (32, 90, 4, 0), (2, 1, 4, 0)])
+def test_gradient_matches_oracle_adjoint(gpu_lib, L, N, nsteps, wgs):
+    say("adjoint", L, N, nsteps, wgs)
+    ctx = lz.make_context(L=L, N=N)
+    x0 = lz.state_from_strings(ctx, double_strings(box_state(400)) if L == 32 else BENCH_X0)
+    xT, ref = grad_sqnorm(ctx, x0, nsteps)
+    p = gpu_lib.Lorenz(L=L, N=N)
+    p.set_schedule(wgs)
+    g64, gbf, fin = p.grad([tuple(v) for v in x0], nsteps)
+    assert fin == [tuple(v) for v in xT]
+    assert gbf == [tuple(v) for v in ref]
+    assert g64 == [to_double(v) for v in ref]
+
+
+def test_gradient_matches_central_differences_of_gpu_runs(gpu_lib):
+    """d||x(T)||^2 / d x0_j from GPU forward runs at x0 +- h, h = 2^-(p/3),
+    to relative 10^-(K/2-10) at K = 100."""
+    K, N, nsteps = 100, 20, 10
+    p = gpu_lib.Lorenz(K=K, N=N)
+    ctx = lz.make_context(K_digits=K, N=N)
+    x0 = lz.state_from_strings(ctx, BENCH_X0)
+    g64, gbf, _ = p.grad([tuple(v) for v in x0], nsteps)
+    h = Fraction(1, 2 ** (ctx.p // 3))
+    tol = Fraction(1, 10 ** (K // 2 - 10))
+
+    def loss(state):
+        fin = p.integrate([tuple(v) for v in state], nsteps)
+        return sum((Fraction(s * m) * Fraction(2) ** e) ** 2 for (s, m, e) in fin)
+
+    for j in range(3):
+        xp, xm = list(x0), list(x0)
+        xp[j] = lz.state_from_fractions(ctx, [x0[j].frac() + h] * 3)[0]
+        xm[j] = lz.state_from_fractions(ctx, [x0[j].frac() - h] * 3)[0]
+        fd = (loss(xp) - loss(xm)) / (2 * h)
+        s, m, e = gbf[j]
+        g = Fraction(s * m) * Fraction(2) ** e
+        assert abs(g - fd) <= tol * abs(fd), j
