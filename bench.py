@@ -2,16 +2,22 @@
 """Benchmark: Taylor steps per second of the multiple-precision Taylor series
 method for the Lorenz system on one MI355X.
 
-Workload lorenz_k2000_n600: sigma=10, R=28, b=8/3 (rounded to p bits),
-K=2000 decimal digits (L=208 32-bit limbs, p=6656 bits), Taylor order N=600,
-tau=1/100, one trajectory from the seeded initial state (seed 2, uniform in
-[-20,20]x[-25,25]x[5,45]).  A "step" is one whole Taylor step: the N
-coefficients of the Leibniz recursion (equation (3)) with their Cauchy sums,
-and the Horner evaluation of the series (equation (2)).
+Default workload lorenz_k2000_n600: sigma=10, R=28, b=8/3 (rounded to p
+bits), K=2000 decimal digits (L=208 32-bit limbs, p=6656 bits), Taylor order
+N=600, tau=1/100, one trajectory from the seeded initial state (seed 2,
+uniform in [-20,20]x[-25,25]x[5,45]).  A "step" is one whole Taylor step:
+the N coefficients of the Leibniz recursion (equation (3)) with their Cauchy
+sums, and the Horner evaluation of the series (equation (2)).
 
 The timed region is one device-resident persistent launch of `--steps`
 steps (inputs already in HBM), bracketed by synchronisations and timed with
 events on the launch stream.  Prints one JSON line.
+
+Other modes (reported separately, not the headline line):
+  --workload lorenz_k100_n40 | lorenz_k4000_n3500   other single trajectories
+  --mode adjoint     forward-with-checkpoints vs reverse-sweep time (K=300, N=90)
+  --mode batch       256-trajectory ensemble in one launch vs one launch each
+  --copy-calibration one device copy of 1 GiB (for counter calibration)
 """
 import argparse
 import json
@@ -22,9 +28,15 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-WORKLOAD = "lorenz_k2000_n600"
-K_DIGITS, N_ORDER = 2000, 600
-INT_VALU_PEAK = 256 * 4 * 16 * 2.4e9  # 32x32-bit multiply-adds per second (full issue rate)
+# 32x32-bit multiply-adds per second at the full VALU issue rate:
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+INT_VALU_PEAK = 256 * 4 * 16 * 2.4e9
+
+SINGLE = {
+    "lorenz_k2000_n600": dict(K=2000, N=600, x0="seed2"),
+    "lorenz_k100_n40": dict(K=100, N=40, x0="bench"),
+    "lorenz_k4000_n3500": dict(K=4000, N=3500, x0="bench"),
+}
 
 
 def limb_macs_per_step(N: int, L: int) -> float:
@@ -35,51 +47,46 @@ def limb_macs_per_step(N: int, L: int) -> float:
     return float(N * (N + 5)) * L * L
 
 
-def oracle_baseline(seconds_budget: float = 20.0):
-    """The oracle, as it stands, on this host: steps of the same workload
-    until the budget is used (at least one)."""
+def initial_state(kind):
+    from workloads import BENCH_X0, box_state
+    if kind == "seed2":
+        return ("double", box_state(2))
+    return ("str", BENCH_X0)
+
+
+def oracle_baseline(workload: str, seconds_budget: float = 20.0):
+    """The oracle, as it stands, on this host: whole steps of the same
+    workload until the budget is used (at least one)."""
     from oracle import lorenz as lz
-    from workloads import box_state, double_strings
-    ctx = lz.make_context(K_digits=K_DIGITS, N=N_ORDER)
-    s = lz.state_from_strings(ctx, double_strings(box_state(2)))
+    from workloads import double_strings
+    w = SINGLE[workload]
+    ctx = lz.make_context(K_digits=w["K"], N=w["N"])
+    kind, v = initial_state(w["x0"])
+    s = lz.state_from_strings(ctx, double_strings(v) if kind == "double" else v)
     n = 0
     t0 = time.perf_counter()
     while True:
         s = lz.step(ctx, s)
         n += 1
         dt = time.perf_counter() - t0
-        if dt >= seconds_budget or n >= 3:
+        if dt >= seconds_budget or n >= 50:
             break
     return {"value": n / dt, "unit": "steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} step(s) of {WORKLOAD} from the seeded state, single-threaded CPython"}
+            "sample": f"{n} step(s) of {workload} from its initial state, single-threaded CPython"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--wgs", type=int, default=0, help="workgroups per trajectory (0: all CUs)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the trajectory's "
-              "coefficient recursion is sequential and this build does not shard it", file=sys.stderr)
-        sys.exit(2)
-
+def run_single(args):
     import torch
     from paper_1908_09301_amd import mpts
-    from workloads import box_state
-
-    torch.cuda.set_device(0)
-    prob = mpts.Lorenz(K=K_DIGITS, N=N_ORDER)
+    w = SINGLE[args.workload]
+    prob = mpts.Lorenz(K=w["K"], N=w["N"])
     if args.wgs:
         prob.set_schedule(args.wgs)
-    x0 = [prob.from_double(v) for v in box_state(2)]
+    kind, v = initial_state(w["x0"])
+    x0 = [prob.from_double(t) for t in v] if kind == "double" else [prob.from_str(t) for t in v]
     x0_dev = prob.pack_state(x0).cuda()
     xout = torch.empty_like(x0_dev)
     ws = prob.workspace(max(args.steps, args.warmup))
-
     if args.warmup > 0:
         prob.integrate_dev(x0_dev, args.warmup, xout, ws=ws)
         prob.check(ws)
@@ -95,35 +102,159 @@ def main():
     wall = time.perf_counter() - t0
     prob.check(ws)
     ms = e0.elapsed_time(e1)
-    ms_per_step = ms / args.steps
-    value = args.steps / (ms * 1e-3)
-    macs = limb_macs_per_step(N_ORDER, prob.L) * args.steps
+    macs = limb_macs_per_step(w["N"], prob.L) * args.steps
     achieved = macs / (ms * 1e-3)
-
     line = {
         "metric": "Taylor steps/s at (K,N)",
-        "value": value,
+        "value": args.steps / (ms * 1e-3),
         "unit": "steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": ms / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "K_digits": K_DIGITS, "N": N_ORDER, "limbs": prob.L,
-                   "p_bits": prob.p, "tau": "1/100", "x0": "seed 2, uniform box",
+        "config": {"workload": args.workload, "K_digits": w["K"], "N": w["N"], "limbs": prob.L,
+                   "p_bits": prob.p, "tau": "1/100",
+                   "x0": "seed 2, uniform box" if w["x0"] == "seed2" else "(-15.8,-17.48,35.64)",
                    "workgroups": args.wgs or "all CUs"},
         "limb_mac_per_s": achieved,
         "wall_s": wall,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT_VALU_PEAK / 1e12,
-                     "unit": "T limb-MAC/s", "frac": achieved / INT_VALU_PEAK, "traffic": None},
+                     "unit": "T limb-MAC/s", "frac": achieved / INT_VALU_PEAK,
+                     "traffic": traffic_from_profiles(args.workload)},
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = oracle_baseline()
+        line["cpu_baseline"] = oracle_baseline(args.workload)
     print(json.dumps(line), flush=True)
+
+
+def traffic_from_profiles(workload: str):
+    """HBM bytes per launch of the forward kernel from the committed counter
+    summary, when it was taken on the current kernel source (else null)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_run_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for ln in open(path):
+        if "=" in ln and not ln.startswith("#"):
+            k, v = ln.split("=", 1)
+            fields[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1908_09301_amd", "csrc")
+    for fn in sorted(os.listdir(csrc)):
+        h.update(open(os.path.join(csrc, fn), "rb").read())
+    if fields.get("source_sha256") != h.hexdigest():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def run_adjoint(args):
+    """Forward run with checkpoints vs the reverse sweep, K=300, N=90."""
+    import torch
+    from paper_1908_09301_amd import mpts
+    from workloads import box_state
+    prob = mpts.Lorenz(K=300, N=90)
+    x0 = [prob.from_double(v) for v in box_state(400)]
+    n = args.steps
+    prob.integrate(x0, 2)  # warm up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prob.integrate(x0, n, checkpoints=True)
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    prob.grad(x0, n)
+    t_grad = time.perf_counter() - t0
+    t_rev = t_grad - t_fwd
+    print(json.dumps({"metric": "adjoint/forward ratio", "workload": "adjoint_k300_n90",
+                      "steps": n, "forward_s": t_fwd, "forward_plus_reverse_s": t_grad,
+                      "reverse_over_forward": t_rev / t_fwd,
+                      "total_over_forward": t_grad / t_fwd}), flush=True)
+
+
+def run_batch(args):
+    """The 256-trajectory ensemble (uneven K, N) in one graph launch vs the
+    same trajectories launched one at a time."""
+    import torch
+    from paper_1908_09301_amd import mpts
+    from workloads import ensemble, perturbed_strings
+    ens = ensemble(seed=3, count=256)
+    by = {}
+    probs, x0s = [], []
+    for e in ens:
+        key = (e["K"], e["N"])
+        if key not in by:
+            by[key] = mpts.Lorenz(K=e["K"], N=e["N"])
+        p = by[key]
+        probs.append(p)
+        x0s.append([p.from_str(v) for v in perturbed_strings(e["delta"])])
+    n = args.steps
+    flags = mpts.MPTS_GRAPH | mpts.MPTS_AUTOTUNE
+    mpts.integrate_batch(probs, x0s, [n] * 256, flags=flags)  # tune, capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mpts.integrate_batch(probs, x0s, [n] * 256, flags=flags)
+    t_batch = time.perf_counter() - t0
+    t_single = 0.0
+    per_class = {}
+    for key, p in by.items():
+        t = [i for i in range(256) if (ens[i]["K"], ens[i]["N"]) == key][0]
+        p.integrate(x0s[t], 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p.integrate(x0s[t], n)
+        per_class[key] = time.perf_counter() - t0
+    for e in ens:
+        t_single += per_class[(e["K"], e["N"])]
+    print(json.dumps({"metric": "batch ratio", "workload": "ensemble256_mixed", "steps": n,
+                      "batch_s": t_batch, "one_launch_each_s": t_single,
+                      "ratio": t_single / t_batch,
+                      "per_class_single_s": {f"{k[0]}/{k[1]}": v for k, v in per_class.items()}}),
+          flush=True)
+
+
+def copy_calibration():
+    import torch
+    a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": 1 << 30}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--wgs", type=int, default=0, help="workgroups per trajectory (0: all CUs)")
+    ap.add_argument("--workload", default="lorenz_k2000_n600", choices=sorted(SINGLE))
+    ap.add_argument("--mode", default="single", choices=["single", "adjoint", "batch"])
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build measures the "
+              "single-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration()
+    elif args.mode == "adjoint":
+        run_adjoint(args)
+    elif args.mode == "batch":
+        run_batch(args)
+    else:
+        run_single(args)
 
 
 if __name__ == "__main__":

@@ -362,8 +362,13 @@ int check_device(mpts_ctx *c) {
     return set_err(c, MPTS_EARCH, std::string("device is ") + pr.gcnArchName + ", need gfx950");
   c->cus = pr.multiProcessorCount;
   c->lds = lds_bytes(c->L, c->N, c->RS, c->WB, c->CM);
-  if (max_coresident(c->CM, c->lds, &c->max_per_cu) != 0 || c->max_per_cu < 1)
-    return set_err(c, MPTS_EUNSUPPORTED, "kernel does not fit one compute unit");
+  int occ = max_coresident(c->CM, c->lds, &c->max_per_cu);
+  if (occ != 0 || c->max_per_cu < 1) {
+    char msg[160];
+    snprintf(msg, sizeof(msg), "kernel does not fit one compute unit (CM %d, LDS %zu bytes, query %d, blocks %d)",
+             c->CM, c->lds, occ, c->max_per_cu);
+    return set_err(c, MPTS_EUNSUPPORTED, msg);
+  }
   return MPTS_OK;
 }
 
@@ -433,12 +438,40 @@ int make_ctx(const char *sigma, const char *R, const char *b, int L, int N, cons
   return MPTS_OK;
 }
 
+// Modelled milliseconds per step of one trajectory on G workgroups: the
+// serial latency per coefficient index (one workgroup, or a group that has
+// to synchronise) plus the product work spread over the group.
+double model_ms(const mpts_ctx *c, int G) {
+  // latency per coefficient index (single workgroup / group synchronisation)
+  // plus the product work spread over G workgroups
+  const double lat = G == 1 ? 0.012 : 0.045;
+  const double digit_macs = (double)c->N * (c->N + 5) * c->nd * (double)c->nd;
+  const double wg_rate = 2.6e13 / 256.0 * 0.25;  // sustained digit-MAC/s of one workgroup
+  return (c->N * 2 * lat) + digit_macs / (G * wg_rate) * 1e3;
+}
+
+// Workgroups for one trajectory when the caller sets none: the power of two
+// (up to the compute-unit count) with the smallest modelled step time.
+int default_groups(const mpts_ctx *c) {
+  int best = 1;
+  double tb = model_ms(c, 1);
+  for (int g = 2; g <= c->cus; g *= 2) {
+    double t = model_ms(c, g);
+    if (t < tb) {
+      tb = t;
+      best = g;
+    }
+  }
+  if (best * 2 > c->cus && model_ms(c, c->cus) <= tb) best = c->cus;
+  return best;
+}
+
 int run_single(mpts_ctx *c, int mode, long long nsteps, const void *x0_dev, void *xout_dev,
                void *ckpt_dev, void *ws, size_t ws_bytes, hipStream_t s, bool x0_on_host,
                const int32_t *x0_host, void *adj_dev = nullptr) {
   int dst = check_device(c);
   if (dst != MPTS_OK) return dst;
-  int G = c->wgs > 0 ? c->wgs : c->cus;
+  int G = c->wgs > 0 ? c->wgs : default_groups(c);
   G = std::min(G, c->cus * c->max_per_cu);
   G = std::max(std::min(G, kMaxWG), 1);
   Layout l = layout(c, nsteps, false, G);
@@ -579,15 +612,6 @@ int batch_layout(mpts_ctx *const *ctxs, int count, BatchLayout &bl) {
 // Measured milliseconds per step of one trajectory class at 1, 2, 4, 8
 // workgroups (filled by the autotuner; keyed by L and N).
 std::map<std::pair<int, int>, std::vector<double>> g_tune;
-
-double model_ms(const mpts_ctx *c, int G) {
-  // latency per coefficient index (single workgroup / group synchronisation)
-  // plus the product work spread over G workgroups
-  const double lat = G == 1 ? 0.012 : 0.045;
-  const double digit_macs = (double)c->N * (c->N + 5) * c->nd * (double)c->nd;
-  const double wg_rate = 2.6e13 / 256.0 * 0.25;  // sustained digit-MAC/s of one workgroup
-  return (c->N * 2 * lat) + digit_macs / (G * wg_rate) * 1e3;
-}
 
 double step_ms(const mpts_ctx *c, int G) {
   auto it = g_tune.find({c->L, c->N});

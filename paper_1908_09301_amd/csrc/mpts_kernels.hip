@@ -183,7 +183,7 @@ size_t lds_bytes(int L, int N, int RS, int WB, int CM) {
   const int maxn = max_terms(N);
   size_t b = (size_t)NFR * WB * 8 + (size_t)3 * 64 * CM * 8 + (size_t)3 * 64 * CM * 4 +
              (size_t)6 * NV * 4 + (size_t)4 * RS * 4 + sizeof(FrameSrc) * NFR +
-             sizeof(FrameD) * (NFR + 1) + 64 * 4 + 2 * NFR * 4 + (size_t)NFR * maxn;
+             sizeof(FrameD) * (NFR + 1) + 64 * 4 + 2 * NFR * 4 + (size_t)maxn;
   return (b + 255) & ~(size_t)255;
 }
 
@@ -217,8 +217,10 @@ __device__ __forceinline__ void copy_norm(const int32_t *src, int32_t *dst, int 
 // the error word so that the host reports it instead of hanging.
 __device__ void spin_until(uint32_t *flag, uint32_t target, uint32_t *err) {
   long long polls = 0;
-  // read-modify-write polls are answered at the coherence point
-  while (__hip_atomic_fetch_add(flag, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+  // device-coherent (sc1) plain loads: they see the other workgroups'
+  // atomics without turning every poll into a write at the coherence point
+  const __amdgpu_buffer_rsrc_t rs = dev_rsrc(flag, 4);
+  while ((uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, 0, 0, 16) < target) {
     __builtin_amdgcn_s_sleep(2);
     if (++polls > (1LL << 25)) {
       atomicOr(err, 4u);
@@ -265,8 +267,8 @@ __device__ void finalize_task(const Inst &I, const Carve &cv, int which, int i,
     const FrameD *fr;
     const long long *fp;
     if (which == 0) {
-      // R a_i - b_i - s1_i
-      ad[0] = Addend{row_ptr(I, 1, i), 1, -1};
+      // R a_i - b_i - s1_i (b_i: this wave's previous result, still in LDS)
+      ad[0] = Addend{res, 0, -1};
       ad[1] = Addend{tmp, 0, -1};
       nad = 2;
       fr = &cv.fd[3];
@@ -329,7 +331,9 @@ __device__ const long long *group_bulk(const Inst &I, const Carve &cv, int nf, i
                                        GroupSync &gs, uint32_t *err) {
   const int tid = threadIdx.x;
   const int G = I.G, WB = I.WB;
-  frame_setup(cv.fs, cv.fd, nf, I.nd, I.RS, cv.red, cv.offs, cv.maxn, err);
+  // the task buffers are idle during the bulk: they hold the exponent sums
+  frame_setup(cv.fs, cv.fd, nf, I.nd, I.RS, cv.red, cv.offs, cv.maxn, (int *)cv.tcols,
+              3 * 64 * I.CM * 2, err);
   frames_accumulate(cv.fs, cv.fd, nf, I.nd, I.RS, WB, cv.lf, rank, G, cv.span, cv.offs, cv.maxn);
   __syncthreads();
   ++gs.nbulk;
@@ -395,10 +399,13 @@ __device__ void start_step(const Inst &I, bool leader, const int32_t *state, Gro
 // The Taylor coefficients 1..N of one step (equation (3)), rows 0 given.
 template <int CM>
 __device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, GroupSync &gs,
-                                     uint32_t *err) {
+                                     const int32_t *state, uint32_t *err) {
   const int tid = threadIdx.x, wave = tid >> 6;
   const bool leader = rank == 0;
   const int RS = I.RS;
+  // the beta task keeps b_i in LDS (its result slot): start with b_0
+  if (leader && wave == 0)
+    copy_norm(state + (I.L + 2), cv.tnorm + cv.NV, I.L, false, threadIdx.x & 63, 64);
   for (int i = 0; i < I.N; ++i) {
     if (tid == 0) {
       FrameSrc *fs = cv.fs;
@@ -497,7 +504,7 @@ __global__ void __launch_bounds__(WGS) k_run(const Inst *__restrict__ insts,
     }
     start_step(I, leader, I.state, gs, err);
     mark(PH_STEP0);
-    forward_coefficients<CM>(I, cv, rank, gs, err);
+    forward_coefficients<CM>(I, cv, rank, gs, I.state, err);
     mark(PH_ACCUM);
     if (I.mode == MODE_COEFFS) break;
     // Horner: h = c_N; h <- round(h tau + c_i), i = N-1..0, three chains at once
@@ -570,7 +577,7 @@ __global__ void __launch_bounds__(WGS) k_adj(const Inst *__restrict__ insts,
   for (long long n = I.nsteps - 1; n >= 0; --n) {
     // 1. the step's coefficients from its checkpoint
     start_step(I, leader, I.ckpt + (size_t)n * 3 * (L + 2), gs, err);
-    forward_coefficients<CM>(I, cv, rank, gs, err);
+    forward_coefficients<CM>(I, cv, rank, gs, I.ckpt + (size_t)n * 3 * (L + 2), err);
     // 2. q^c_0 = incoming adjoint, q^c_i = round(q^c_{i-1} tau)
     if (leader) {
       if (wave < 3) {
@@ -730,12 +737,21 @@ hipError_t launch_adj(const Inst *d_insts, const int *d_wg_inst, int nwg, int CM
   }
 }
 
+template <int CM>
+static hipError_t set_lds_cm(size_t lds) {
+  hipError_t e = hipFuncSetAttribute((const void *)k_run<CM>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void *)k_adj<CM>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds);
+}
+
 hipError_t set_kernel_lds(int CM, size_t lds) {
   switch (CM) {
-    case 4: return hipFuncSetAttribute((const void *)k_run<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    case 8: return hipFuncSetAttribute((const void *)k_run<8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    case 16: return hipFuncSetAttribute((const void *)k_run<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    case 32: return hipFuncSetAttribute((const void *)k_run<32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    case 4: return set_lds_cm<4>(lds);
+    case 8: return set_lds_cm<8>(lds);
+    case 16: return set_lds_cm<16>(lds);
+    case 32: return set_lds_cm<32>(lds);
     default: return hipErrorInvalidValue;
   }
 }
@@ -751,16 +767,37 @@ hipError_t launch_clear(void *p, size_t bytes, hipStream_t s) {
 
 int max_coresident(int CM, size_t lds, int *out) {
   int nb = 0;
-  hipError_t e;
+  // the occupancy query honours the kernels' dynamic-LDS limit: raise it first
+  hipError_t e = set_kernel_lds(CM, lds);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();  // do not leave the failure for the next launch to report
+    return -1;
+  }
+  int na = 0;
   switch (CM) {
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_run<4>, WGS, lds); break;
-    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_run<8>, WGS, lds); break;
-    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_run<16>, WGS, lds); break;
-    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_run<32>, WGS, lds); break;
+    case 4:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_run<4>, WGS, lds);
+      if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&na, k_adj<4>, WGS, lds);
+      break;
+    case 8:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_run<8>, WGS, lds);
+      if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&na, k_adj<8>, WGS, lds);
+      break;
+    case 16:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_run<16>, WGS, lds);
+      if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&na, k_adj<16>, WGS, lds);
+      break;
+    case 32:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_run<32>, WGS, lds);
+      if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&na, k_adj<32>, WGS, lds);
+      break;
     default: return -1;
   }
-  if (e != hipSuccess) return -1;
-  *out = nb;
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return -2;
+  }
+  *out = nb < na ? nb : na;
   return 0;
 }
 

@@ -237,24 +237,31 @@ __device__ __forceinline__ void tile_normalize(long long (&acc)[16]) {
 // are all-zero digits).  Every thread of the workgroup calls this.
 // red: 4 waves x 2 NFR ints.
 __device__ void frame_setup(const FrameSrc *fs, FrameD *fd, int nf, int nd, int RS, int *red,
-                            int8_t *offs, int maxn, uint32_t *err) {
+                            int8_t *offs, int maxn, int *esum, int esum_cap, uint32_t *err) {
   const int tid = threadIdx.x;
   const int MT = (nd + TQ - 1) / TQ;
   int mn[NFR], mx[NFR];
+  // one pass over the row headers: exponent sums kept in LDS (esum, laid
+  // out frame after frame; INT_MIN marks a zero term) for the offset pass
+  int eb = 0;
 #pragma unroll
   for (int f = 0; f < NFR; ++f) {
     mn[f] = 0x7fffffff;
     mx[f] = -0x7fffffff;
     if (f < nf) {
+      const bool keep = eb + fs[f].n <= esum_cap;
       for (int k = tid; k < fs[f].n; k += WGS) {
         const int32_t *U, *V;
         frame_term(fs[f], k, RS, &U, &V);
+        int e = (int)0x80000000;
         if (U[1] != 0 && V[1] != 0) {
-          int e = U[0] + V[0];
+          e = U[0] + V[0];
           mn[f] = min(mn[f], e);
           mx[f] = max(mx[f], e);
         }
+        if (keep) esum[eb + k] = e;
       }
+      eb += fs[f].n;
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -305,19 +312,29 @@ __device__ void frame_setup(const FrameSrc *fs, FrameD *fd, int nf, int nd, int 
     }
   }
   __syncthreads();
+  eb = 0;
   for (int f = 0; f < nf; ++f) {
     const int base = fd[f].base, S = fd[f].S;
-    if (fd[f].obase + fs[f].n > maxn) continue;
-    for (int k = tid; k < fs[f].n; k += WGS) {
-      const int32_t *U, *V;
-      frame_term(fs[f], k, RS, &U, &V);
-      int off = 0;
-      if (U[1] != 0 && V[1] != 0) {
-        off = U[0] + V[0] - base;
-        if (off < 0 || off > S) off = 0;  // only after a spread error (already flagged)
+    const bool keep = eb + fs[f].n <= esum_cap;
+    if (fd[f].obase + fs[f].n <= maxn) {
+      for (int k = tid; k < fs[f].n; k += WGS) {
+        int e;
+        if (keep) {
+          e = esum[eb + k];
+        } else {
+          const int32_t *U, *V;
+          frame_term(fs[f], k, RS, &U, &V);
+          e = (U[1] != 0 && V[1] != 0) ? U[0] + V[0] : (int)0x80000000;
+        }
+        int off = 0;
+        if (e != (int)0x80000000) {
+          off = e - base;
+          if (off < 0 || off > S) off = 0;  // only after a spread error (already flagged)
+        }
+        offs[fd[f].obase + k] = (int8_t)off;
       }
-      offs[fd[f].obase + k] = (int8_t)off;
     }
+    eb += fs[f].n;
   }
   __syncthreads();
 }
@@ -460,34 +477,48 @@ __device__ void frames_accumulate(const FrameSrc *fs, const FrameD *fd, int nf, 
     }
     const int8_t *of = offs + fd[f].obase;
     const int Sf = fd[f].S;
-    const FrameSrc src = fs[f];
-    int32_t ua[TQ], va[TQ], ub[TQ], vb[TQ];
-    const int32_t *U, *V;
-    frame_term(src, k0, RS, &U, &V);
-    tile_load(ua, va, U, V, mt, nt, min(max((int)of[k0], 0), Sf));
+    const FrameSrc &src = fs[f];
+    // walk the segment part by part with pointer strides (no per-term dispatch)
     int k = k0;
     while (k < k1) {
-      if (k + 1 < k1) {
-        frame_term(src, k + 1, RS, &U, &V);
-        tile_load(ub, vb, U, V, mt, nt, min(max((int)of[k + 1], 0), Sf));
+      int j = 0, kl = k;
+      while (j + 1 < src.nparts && kl >= src.p[j].n) {
+        kl -= src.p[j].n;
+        ++j;
       }
-      tile_fma(acc, ua, va);
-      if (++since == FLUSH_TERMS) {
-        tile_normalize(acc);
-        since = 0;
+      const FramePart &pt = src.p[j];
+      const int kend = min(k1, k - kl + pt.n);
+      const int32_t *U, *V;
+      part_term(pt, kl, RS, &U, &V);
+      const long long dU = pt.kind == PK_CAUCHY ? -(long long)RS : (pt.kind == PK_ONE ? 0 : RS);
+      const long long dV = pt.kind == PK_ONE ? 0 : RS;
+      int32_t ua[TQ], va[TQ], ub[TQ], vb[TQ];
+      tile_load(ua, va, U, V, mt, nt, min(max((int)of[k], 0), Sf));
+      while (k < kend) {
+        if (k + 1 < kend) {
+          U += dU;
+          V += dV;
+          tile_load(ub, vb, U, V, mt, nt, min(max((int)of[k + 1], 0), Sf));
+        }
+        tile_fma(acc, ua, va);
+        if (++since == FLUSH_TERMS) {
+          tile_normalize(acc);
+          since = 0;
+        }
+        ++k;
+        if (k >= kend) break;
+        if (k + 1 < kend) {
+          U += dU;
+          V += dV;
+          tile_load(ua, va, U, V, mt, nt, min(max((int)of[k + 1], 0), Sf));
+        }
+        tile_fma(acc, ub, vb);
+        if (++since == FLUSH_TERMS) {
+          tile_normalize(acc);
+          since = 0;
+        }
+        ++k;
       }
-      ++k;
-      if (k >= k1) break;
-      if (k + 1 < k1) {
-        frame_term(src, k + 1, RS, &U, &V);
-        tile_load(ua, va, U, V, mt, nt, min(max((int)of[k + 1], 0), Sf));
-      }
-      tile_fma(acc, ub, vb);
-      if (++since == FLUSH_TERMS) {
-        tile_normalize(acc);
-        since = 0;
-      }
-      ++k;
     }
     q = seg_end;
   }

@@ -335,3 +335,60 @@ def integrate_batch(problems: Sequence[Lorenz], x0s, nsteps: Sequence[int], flag
         res.append(r)
     del Lmax
     return res
+
+
+def _exact_sqnorm(state) -> float:
+    """||x||^2 of a big-float state, computed exactly and rounded once to
+    FP64 (CPython's int/int division is correctly rounded)."""
+    from fractions import Fraction
+    tot = Fraction(0)
+    for (s, m, e) in state:
+        if s:
+            tot += (Fraction(m) * Fraction(2) ** e) ** 2
+    return tot.numerator / tot.denominator
+
+
+def _make_sqnorm_function():
+    import torch
+
+    class LorenzSqNorm(torch.autograd.Function):
+        """loss = ||x(T)||^2 after `nsteps` Taylor steps of `problem` from x0.
+
+        Inputs: x0, a float64 tensor of 3 values (taken exactly), and params,
+        a float64 tensor (sigma, R, b) that must equal the problem's own
+        parameters to double precision; the arithmetic uses the problem's
+        p-bit parameters (b = 8/3 rounded to p bits, not its double).  The
+        forward value is the FP64 rounding of the exact loss of the p-bit
+        state; backward returns grad_output times the p-bit gradient rounded
+        to FP64, for x0 and for params (the b derivative taken at the p-bit b).
+        """
+
+        @staticmethod
+        def forward(ctx, x0, params, problem, nsteps):
+            xs = [problem.from_double(float(v)) for v in x0.detach().cpu().tolist()]
+            want = [problem.to_double(problem.param(j)) for j in range(3)]
+            got = [float(v) for v in params.detach().cpu().tolist()]
+            if got != want:
+                raise ValueError(f"params {got} differ from the problem's {want}")
+            g64, _, fin = problem.grad(xs, nsteps)
+            ctx.save_for_backward(torch.tensor(g64, dtype=torch.float64))
+            return torch.tensor(_exact_sqnorm(fin), dtype=torch.float64, device=x0.device)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (g,) = ctx.saved_tensors
+            go = grad_out.detach().to("cpu", torch.float64)
+            return (go * g[:3]).to(grad_out.device), (go * g[3:]).to(grad_out.device), None, None
+
+    return LorenzSqNorm
+
+
+class _Lazy:
+    fn = None
+
+
+def LorenzSqNorm():
+    """The torch.autograd.Function for ||x(T)||^2 (created on first use)."""
+    if _Lazy.fn is None:
+        _Lazy.fn = _make_sqnorm_function()
+    return _Lazy.fn

@@ -57,3 +57,18 @@ def test_gradient_matches_central_differences_of_gpu_runs(gpu_lib):
         s, m, e = gbf[j]
         g = Fraction(s * m) * Fraction(2) ** e
         assert abs(g - fd) <= tol * abs(fd), j
+
+
+def test_autograd_function_matches_grad(gpu_lib):
+    import torch
+    p = gpu_lib.Lorenz(K=100, N=20)
+    x0 = torch.tensor([-15.8, -17.48, 35.64], dtype=torch.float64, requires_grad=True)
+    params = torch.tensor([10.0, 28.0, p.to_double(p.param(2))], dtype=torch.float64,
+                          requires_grad=True)
+    fn = gpu_lib.LorenzSqNorm()
+    loss = fn.apply(x0, params, p, 6)
+    (3.0 * loss).backward()
+    g64, _, fin = p.grad([p.from_double(v) for v in (-15.8, -17.48, 35.64)], 6)
+    assert loss.item() == gpu_lib._exact_sqnorm(fin)
+    assert x0.grad.tolist() == [3.0 * v for v in g64[:3]]
+    assert params.grad.tolist() == [3.0 * v for v in g64[3:]]
