@@ -27,8 +27,13 @@ constexpr int FLUSH_TERMS = 15;                // terms between accumulator carr
 // constant rows (each a p-bit value converted to a row at kernel start)
 enum { C_SIGMA = 0, C_NSIGMA, C_R, C_NB, C_TAU, C_ONE, NCONST };
 
-// sync words, each on its own 128-byte line
-enum { SY_ARRIVE = 0, SY_FLAG = 32, SY_ERROR = 64, SY_WORDS = 96 };
+// sync words, each on its own 128-byte line: NSPLIT arrival counters and
+// NSPLIT copies of the publication flag (workgroup r uses copy r mod NSPLIT,
+// so that no single line takes every workgroup's atomics or polls), the
+// error word and the Horner completion counter
+constexpr int NSPLIT = 8;
+enum { SY_ARRIVE = 0, SY_FLAG = 32 * NSPLIT, SY_ERROR = 64 * NSPLIT, SY_HDONE = 64 * NSPLIT + 32,
+       SY_WORDS = 64 * NSPLIT + 64 };
 
 enum { MODE_INTEGRATE = 0, MODE_COEFFS = 1, MODE_ADJOINT = 2 };
 
@@ -39,10 +44,18 @@ inline int row_stride(int nd) { int rs = HDR + RPAD + nd + RPAD + TQ; return (rs
 inline int frame_width(int nd) { int w = 2 * nd + SMAX + 2 * TQ + 8; return (w + 31) & ~31; }
 // digits one single-wave big-integer task must hold (combine + division)
 inline int task_digits(int nd) { return 3 * nd + 2 * SMAX + 48; }
-// bytes of the per-term offset table: the frames of one index hold at most
-// 5 (N + 1) terms (forward) or 3 (2N + 2) terms (adjoint), each frame's
-// slice rounded up to 16
-__host__ __device__ inline int max_terms(int N) { return 6 * N + 6 + 5 * 16; }
+// bytes of the adjoint's per-term offset tables: its frames of one index
+// hold at most 4 N + 4 terms in at most 8 parts without exponent caches,
+// each part's slice rounded up to 16
+__host__ __device__ inline int adj_table_bytes(int N) { return 4 * N + 4 + 8 * 16; }
+
+// Address-space views of pointers whose memory kind is known: loads through
+// them compile to global_load / ds_read (waited for with their own counters)
+// instead of flat accesses, which make every wait cover all memory in flight.
+typedef __attribute__((address_space(1))) int32_t g_i32;
+typedef __attribute__((address_space(3))) int32_t l_i32;
+typedef __attribute__((address_space(3))) long long l_i64;
+typedef __attribute__((address_space(3))) int8_t l_i8;
 
 struct Inst {
   int L, N, nd, RS, WB, CM;  // limbs, order, digits/row, row stride, frame width, chunk max
@@ -66,5 +79,6 @@ struct Inst {
 // phases timed when Inst::prof is set (leader slots 0..15, one follower 16..31)
 enum { PH_SETUP = 0, PH_ACCUM, PH_FLUSH, PH_WAIT, PH_FINAL, PH_CLEAR, PH_HORNER, PH_STEP0,
        PH_NPHASE = 16 };
+constexpr int PROF_RANK = 8;  // per-workgroup profile words
 
 }  // namespace mpts

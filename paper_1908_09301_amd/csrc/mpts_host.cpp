@@ -288,6 +288,9 @@ struct mpts_ctx {
   int cus = 0;
   int max_per_cu = 0;
   size_t lds = 0;
+  int last_G = 0;            // workgroups of the last single-trajectory launch
+  int max_per_cu_adj = -1;  // -1: not queried yet; 0: the adjoint kernel does not fit
+  size_t lds_adj = 0;
   std::string err;
 };
 
@@ -321,7 +324,7 @@ Layout layout(const mpts_ctx *c, long long nsteps, bool ckpt, int nwg) {
   Layout l;
   size_t o = 0;
   l.prof = o;
-  o = al(o + 2 * PH_NPHASE * 8);
+  o = al(o + (2 * PH_NPHASE + (size_t)kMaxWG * PROF_RANK) * 8);
   l.sync = o;
   o = al(o + SY_WORDS * 4);
   l.cnorm = o;
@@ -361,8 +364,8 @@ int check_device(mpts_ctx *c) {
   if (strncmp(pr.gcnArchName, "gfx950", 6) != 0)
     return set_err(c, MPTS_EARCH, std::string("device is ") + pr.gcnArchName + ", need gfx950");
   c->cus = pr.multiProcessorCount;
-  c->lds = lds_bytes(c->L, c->N, c->RS, c->WB, c->CM);
-  int occ = max_coresident(c->CM, c->lds, &c->max_per_cu);
+  c->lds = lds_bytes(c->L, c->N, c->RS, c->WB, c->CM, false);
+  int occ = max_coresident(c->CM, c->lds, &c->max_per_cu, false);
   if (occ != 0 || c->max_per_cu < 1) {
     char msg[160];
     snprintf(msg, sizeof(msg), "kernel does not fit one compute unit (CM %d, LDS %zu bytes, query %d, blocks %d)",
@@ -471,8 +474,16 @@ int run_single(mpts_ctx *c, int mode, long long nsteps, const void *x0_dev, void
                const int32_t *x0_host, void *adj_dev = nullptr) {
   int dst = check_device(c);
   if (dst != MPTS_OK) return dst;
+  const bool adj = mode == MODE_ADJOINT;
+  if (adj && c->max_per_cu_adj < 0) {
+    c->lds_adj = lds_bytes(c->L, c->N, c->RS, c->WB, c->CM, true);
+    int occ = max_coresident(c->CM, c->lds_adj, &c->max_per_cu_adj, true);
+    if (occ != 0) c->max_per_cu_adj = 0;
+  }
+  if (adj && c->max_per_cu_adj < 1)
+    return set_err(c, MPTS_EUNSUPPORTED, "adjoint kernel does not fit one compute unit");
   int G = c->wgs > 0 ? c->wgs : default_groups(c);
-  G = std::min(G, c->cus * c->max_per_cu);
+  G = std::min(G, c->cus * (adj ? std::min(c->max_per_cu, c->max_per_cu_adj) : c->max_per_cu));
   G = std::max(std::min(G, kMaxWG), 1);
   Layout l = layout(c, nsteps, false, G);
   if (ws_bytes < l.total) return set_err(c, MPTS_ENOSPC, "workspace too small");
@@ -480,7 +491,7 @@ int run_single(mpts_ctx *c, int mode, long long nsteps, const void *x0_dev, void
   hipError_t e;
   const bool phases = getenv("MPTS_PHASES") != nullptr;
   if (phases) {
-    e = launch_clear(base + l.prof, 2 * PH_NPHASE * 8, s);
+    e = launch_clear(base + l.prof, (2 * PH_NPHASE + (size_t)G * PROF_RANK) * 8, s);
     if (e != hipSuccess) return hip_err(c, e, "clear");
   }
   e = launch_clear(base + l.sync, SY_WORDS * 4, s);
@@ -515,12 +526,14 @@ int run_single(mpts_ctx *c, int mode, long long nsteps, const void *x0_dev, void
   I.sync = (uint32_t *)(base + l.sync);
   I.adj = (int32_t *)adj_dev;
   I.prof = phases ? (unsigned long long *)(base + l.prof) : nullptr;
+  c->last_G = G;
   e = hipMemcpyAsync(base + l.inst, &I, sizeof(I), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_err(c, e, "copy descriptor");
   e = launch_clear(base + l.wgmap, (size_t)G * 4, s);
   if (e != hipSuccess) return hip_err(c, e, "clear");
   if (mode == MODE_ADJOINT)
-    e = launch_adj((const Inst *)(base + l.inst), (const int *)(base + l.wgmap), G, c->CM, c->lds, s);
+    e = launch_adj((const Inst *)(base + l.inst), (const int *)(base + l.wgmap), G, c->CM, c->lds_adj,
+                   s);
   else
     e = launch_run((const Inst *)(base + l.inst), (const int *)(base + l.wgmap), G, c->CM, c->lds,
                    s, true);
@@ -547,18 +560,49 @@ int read_status(mpts_ctx *c, void *ws, hipStream_t s) {
       (void)hipGetDevice(&dev);
       (void)hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev);
       double us = rate > 0 ? 1e3 / rate : 0.0;  // rate in kHz
-      static const char *nm[13] = {"setup", "accum", "flush", "wait", "final", "clear", "horner",
-                                   "step0", "f.res1", "f.round1", "f.res2", "f.div", "f.row"};
+      static const char *nm[16] = {"setup", "accum", "flush", "wait", "final", "release", "horner",
+                                   "step0", "f.res1", "f.round1", "f.res2", "f.div", "f.row", "h.prod", "h.res", "h.round"};
       fprintf(stderr, "mpts phases (us):");
       for (int w2 = 0; w2 < 2; ++w2) {
         fprintf(stderr, w2 ? "\n  wg1:" : "\n  leader:");
-        for (int j = 0; j < (w2 ? 8 : 13); ++j) fprintf(stderr, " %s=%.1f", nm[j], ph[w2 * PH_NPHASE + j] * us);
+        for (int j = 0; j < (w2 ? 8 : 16); ++j) fprintf(stderr, " %s=%.1f", nm[j], ph[w2 * PH_NPHASE + j] * us);
       }
       fprintf(stderr, "\n");
+      const int G = c->last_G;
+      std::vector<unsigned long long> pr((size_t)G * PROF_RANK);
+      if (G > 0 && hipMemcpy(pr.data(), (char *)ws + l.prof + 2 * PH_NPHASE * 8, pr.size() * 8,
+                             hipMemcpyDeviceToHost) == hipSuccess) {
+        static const char *rn[4] = {"setup", "accum", "flush", "release"};
+        for (int q = 0; q < 4; ++q) {
+          std::vector<std::pair<double, int>> v;
+          for (int r = 0; r < G; ++r) v.push_back({pr[(size_t)r * PROF_RANK + q] * us, r});
+          std::sort(v.begin(), v.end());
+          fprintf(stderr, "  per-wg %s: min %.1f (wg %d) med %.1f max %.1f (wg %d) p90 %.1f\n", rn[q],
+                  v[0].first, v[0].second, v[G / 2].first, v[G - 1].first, v[G - 1].second,
+                  v[(G * 9) / 10].first);
+        }
+        std::map<unsigned, int> cu;
+        int xcc_ok = 0;
+        for (int r = 0; r < G; ++r) {
+          unsigned x = (unsigned)pr[(size_t)r * PROF_RANK + 4], hw = (unsigned)pr[(size_t)r * PROF_RANK + 5];
+          cu[(x << 16) | ((hw >> 8) & 0xff)]++;
+          if ((int)x == r % 8) ++xcc_ok;
+        }
+        int shared = 0;
+        for (auto &kv : cu) shared += kv.second > 1 ? kv.second : 0;
+        fprintf(stderr, "  placement: %d of %d workgroups on xcc rank%%8; %d distinct (xcc, cu/se) slots, %d workgroups sharing one\n",
+                xcc_ok, G, (int)cu.size(), shared);
+      }
     }
   }
   if (w & 4u) return set_err(c, MPTS_EHIP, "device synchronisation timed out");
-  if (w & 3u) return set_err(c, MPTS_ERANGE, "exact sum outside the device window or exponent overflow");
+  if (w & 8u) return set_err(c, MPTS_EUNSUPPORTED, "per-term offset table overflow");
+  if (w & 3u) {
+    char msg[96];
+    snprintf(msg, sizeof(msg), "%s (device status 0x%x)",
+             (w & 1u) ? "exact sum outside the device window" : "exponent overflow in rounding", w);
+    return set_err(c, MPTS_ERANGE, msg);
+  }
   return MPTS_OK;
 }
 
@@ -604,7 +648,7 @@ int batch_layout(mpts_ctx *const *ctxs, int count, BatchLayout &bl) {
   if (bl.CM < 0) return MPTS_EUNSUPPORTED;
   for (int t = 0; t < count; ++t) {
     mpts_ctx *c = ctxs[t];
-    bl.lds = std::max(bl.lds, lds_bytes(c->L, c->N, c->RS, c->WB, bl.CM));
+    bl.lds = std::max(bl.lds, lds_bytes(c->L, c->N, c->RS, c->WB, bl.CM, false));
   }
   return MPTS_OK;
 }
@@ -673,7 +717,7 @@ int plan_batch(mpts_ctx *const *ctxs, int count, const int64_t *nsteps, const Ba
                bool autotune, void *ws, size_t ws_bytes, hipStream_t s, std::vector<int> &G) {
   mpts_ctx *c0 = ctxs[0];
   int per_cu = 0;
-  if (max_coresident(bl.CM, bl.lds, &per_cu) != 0 || per_cu < 1)
+  if (max_coresident(bl.CM, bl.lds, &per_cu, false) != 0 || per_cu < 1)
     return set_err(c0, MPTS_EUNSUPPORTED, "kernel does not fit one compute unit");
   const int cap = std::min(c0->cus * per_cu, kMaxWG);
   if (count > cap) return set_err(c0, MPTS_EUNSUPPORTED, "more trajectories than resident workgroups");
@@ -1028,7 +1072,7 @@ int mpts_integrate_batch(mpts_ctx *const *ctxs, int32_t count, const mpts_bf *x0
       // capture on a private stream (the caller's may be the legacy default
       // stream, which cannot be captured); the graph is launched on the
       // caller's stream below
-      e = set_kernel_lds(bl.CM, bl.lds);
+      e = set_kernel_lds(bl.CM, bl.lds, false);
       if (e != hipSuccess) return hip_err(c0, e, "kernel attributes");
       hipStream_t cap;
       e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);

@@ -6,8 +6,8 @@
 
 namespace mpts {
 
-// Bytes of dynamic LDS one workgroup of the forward kernel needs.
-size_t lds_bytes(int L, int N, int RS, int WB, int CM);
+// Bytes of dynamic LDS one workgroup of the forward (or adjoint) kernel needs.
+size_t lds_bytes(int L, int N, int RS, int WB, int CM, bool adjoint);
 
 // Launch of the persistent forward kernel over `nwg` workgroups; workgroup w
 // runs trajectory d_insts[d_wg_inst[w]].  `cooperative` asks the runtime to
@@ -20,13 +20,13 @@ hipError_t launch_run(const Inst *d_insts, const int *d_wg_inst, int nwg, int CM
 hipError_t launch_adj(const Inst *d_insts, const int *d_wg_inst, int nwg, int CM, size_t lds,
                       hipStream_t s);
 
-// Allow the forward kernel instance for CM the given dynamic LDS size.
-hipError_t set_kernel_lds(int CM, size_t lds);
+// Allow the forward (or adjoint) kernel instance for CM the given dynamic LDS size.
+hipError_t set_kernel_lds(int CM, size_t lds, bool adjoint);
 
 // Zero `bytes` of device memory with a kernel (usable under graph capture).
 hipError_t launch_clear(void *p, size_t bytes, hipStream_t s);
 
-// Workgroups of the forward kernel that fit on one compute unit.
-int max_coresident(int CM, size_t lds, int *out);
+// Workgroups of the forward (or adjoint) kernel that fit on one compute unit.
+int max_coresident(int CM, size_t lds, int *out, bool adjoint);
 
 }  // namespace mpts

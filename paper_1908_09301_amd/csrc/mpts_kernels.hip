@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 #include "mpts_common.h"
 #include "mpts_wave.h"
+#include "mpts_digits.h"
 #include "mpts_rows.h"
 #include "mpts_kernels.h"
 
@@ -29,9 +30,10 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 struct Addend {
-  const int32_t *p;  // row (is_row) or normalised value [sign, E, M]
+  const int32_t *p;  // row (is_row; global memory) or normalised value [sign, E, M]
   int is_row;
   int sgn;
+  int lds;           // a normalised value in LDS (else in global memory)
 };
 
 // Exact sum of one product frame (columns from global memory or LDS) and up
@@ -39,7 +41,7 @@ struct Addend {
 // Each lane gathers its own chunk of columns straight into registers.
 // Single wavefront.
 template <int CM>
-__device__ int combine_resolve(const long long *frame, bool frame_global, const FrameD *fd,
+__device__ __forceinline__ int combine_resolve(const long long *frame, bool frame_global, const FrameD *fd,
                                int nd, int L, const Addend *adds, int nadd, int32_t *dig,
                                int *C, long long *dexp, uint32_t *err) {
   const int lane = lane_id();
@@ -56,12 +58,21 @@ __device__ int combine_resolve(const long long *frame, bool frame_global, const 
     long long e;
     int s;
     ash[a] = 0;
-    if (adds[a].is_row) {
-      e = adds[a].p[0];
-      s = adds[a].p[1];
+    const int32_t *ap = adds[a].p;
+    int h0, h1;
+    if (adds[a].lds) {
+      h0 = ((const l_i32 *)ap)[0];
+      h1 = ((const l_i32 *)ap)[1];
     } else {
-      s = adds[a].p[0];
-      e = floordiv28(adds[a].p[1], &ash[a]);
+      h0 = ((const g_i32 *)ap)[0];
+      h1 = ((const g_i32 *)ap)[1];
+    }
+    if (adds[a].is_row) {
+      e = h0;
+      s = h1;
+    } else {
+      s = h0;
+      e = floordiv28(h1, &ash[a]);
     }
     ae[a] = e;
     as[a] = s;
@@ -98,11 +109,13 @@ __device__ int combine_resolve(const long long *frame, bool frame_global, const 
         v[j] = ld_dev64(rs, off);
       }
     } else {
+      const l_i64 *lfr = (const l_i64 *)frame;
 #pragma unroll
       for (int j = 0; j < CM; ++j) {
-        if (j >= Cc) break;
-        int fc = c0 + j - o;
-        if (fc >= 0 && fc < fcols) v[j] = frame[fc];
+        if (j < Cc) {
+          int fc = c0 + j - o;
+          if (fc >= 0 && fc < fcols) v[j] = lfr[fc];
+        }
       }
     }
   }
@@ -111,20 +124,36 @@ __device__ int combine_resolve(const long long *frame, bool frame_global, const 
     const int o = (int)(ae[a] - lo);
     const long long sg = adds[a].sgn;
     if (adds[a].is_row) {
-      const int32_t *row = adds[a].p + HDR + RPAD;
+      // digits of the row (global): gathered branch-free through a buffer
+      // resource, whose range check reads 0 outside the row's digits
+      const __amdgpu_buffer_rsrc_t rs = dev_rsrc(adds[a].p + HDR + RPAD, nd * 4);
 #pragma unroll
       for (int j = 0; j < CM; ++j) {
-        if (j >= Cc) break;
-        int k = c0 + j - o;
-        if (k >= 0 && k < nd) v[j] += sg * row[k];
+        const int k = c0 + j - o;
+        const int off = (j < Cc && k >= 0) ? k * 4 : 0x7ffffff0;
+        v[j] += sg * (long long)(int32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
       }
     } else {
       const long long sgs = sg * as[a];
+      const int sh = (int)ash[a];
+      if (adds[a].lds) {
+        const l_i32 *M = (const l_i32 *)(adds[a].p + 2);
 #pragma unroll
-      for (int j = 0; j < CM; ++j) {
-        if (j >= Cc) break;
-        int k = c0 + j - o;
-        if (k >= 0 && k < nd) v[j] += sgs * (long long)mant_bits28(adds[a].p + 2, L, (long long)DBITS * k - ash[a]);
+        for (int j = 0; j < CM; ++j) {
+          if (j < Cc) {
+            int k = c0 + j - o;
+            if (k >= 0 && k < nd) v[j] += sgs * (long long)mant_bits28_l(M, L, DBITS * k - sh);
+          }
+        }
+      } else {
+        const g_i32 *M = (const g_i32 *)(adds[a].p + 2);
+#pragma unroll
+        for (int j = 0; j < CM; ++j) {
+          if (j < Cc) {
+            int k = c0 + j - o;
+            if (k >= 0 && k < nd) v[j] += sgs * (long long)mant_bits28_g(M, L, DBITS * k - sh);
+          }
+        }
       }
     }
   }
@@ -135,18 +164,185 @@ __device__ int combine_resolve(const long long *frame, bool frame_global, const 
   return sgn;
 }
 
+// A row addend of a gather: row (global memory, or LDS when lds), times sgn.
+struct RowAdd {
+  const int32_t *row;
+  int sgn;
+  int lds;
+};
+
+// Digit window [lo, lo + W) of the exact sum of a product frame and up to
+// three row addends (W includes two digits of headroom for carries).  Sets
+// *C = ceil(W / 64) (at least 2) and the addends' exponents and signs.
+// Returns false, flagging the error word, when the window needs more than
+// the task's 64 CM digits; a sum with no nonzero operand has C = 2, lo = 0.
+template <int CM>
+__device__ __forceinline__ bool sum_window(const FrameD *fd, int nd, const RowAdd *adds, int nadd,
+                                           long long *lo_out, int *C, int *ae, int *as,
+                                           uint32_t *err) {
+  long long lo = (1LL << 40), hi = -(1LL << 40);
+  if (fd && fd->nz) {
+    lo = fd->base;
+    hi = (long long)fd->base + frame_cols(*fd, nd);
+  }
+  for (int a = 0; a < nadd; ++a) {
+    if (adds[a].lds) {
+      ae[a] = ((const l_i32 *)adds[a].row)[0];
+      as[a] = ((const l_i32 *)adds[a].row)[1];
+    } else {
+      ae[a] = ((const g_i32 *)adds[a].row)[0];
+      as[a] = ((const g_i32 *)adds[a].row)[1];
+    }
+    if (as[a] != 0) {
+      lo = min(lo, (long long)ae[a]);
+      hi = max(hi, (long long)ae[a] + nd);
+    }
+  }
+  *C = 2;
+  *lo_out = 0;
+  if (lo > hi) return true;
+  if (hi - lo + 2 > 64LL * CM) {
+    if (lane_id() == 0) atomicOr(err, 1u | 32u);
+    return false;
+  }
+  const int W = (int)(hi - lo + 2);
+  *C = W > 128 ? (W + 63) >> 6 : 2;
+  *lo_out = lo;
+  return true;
+}
+
+// The sum of sum_window, gathered into registers (lane l: columns
+// [l C, l C + C) over 2^(28 lo)) and resolved into sign and magnitude
+// digits.  Single wavefront.
+template <int C>
+__device__ __forceinline__ int gather_c(const long long *frame, bool frame_global, const FrameD *fd,
+                                        int nd, const RowAdd *adds, int nadd, const int *ae,
+                                        const int *as, long long lo, int (&d)[C], uint32_t *err) {
+  const int lane = lane_id();
+  const int c0 = lane * C;
+  long long v[C];
+#pragma unroll
+  for (int j = 0; j < C; ++j) v[j] = 0;
+  if (fd && fd->nz) {
+    const int fcols = frame_cols(*fd, nd);
+    const int o = (int)(fd->base - lo);
+    if (frame_global) {
+      // branch-free: offsets outside the frame read 0
+      const __amdgpu_buffer_rsrc_t rs = dev_rsrc(frame, fcols * 8);
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        const int fc = c0 + j - o;
+        v[j] = ld_dev64(rs, fc >= 0 ? fc * 8 : 0x7ffffff0);
+      }
+    } else {
+      const l_i64 *lfr = (const l_i64 *)frame;
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        const int fc = c0 + j - o;
+        if (fc >= 0 && fc < fcols) v[j] = lfr[fc];
+      }
+    }
+  }
+  for (int a = 0; a < nadd; ++a) {
+    if (as[a] == 0) continue;
+    const int o = (int)(ae[a] - lo);
+    const long long sg = adds[a].sgn;
+    if (adds[a].lds) {
+      const l_i32 *dg = (const l_i32 *)adds[a].row + HDR + RPAD;
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        const int k = c0 + j - o;
+        if (k >= 0 && k < nd) v[j] += sg * (long long)dg[k];
+      }
+    } else {
+      const __amdgpu_buffer_rsrc_t rs = dev_rsrc(adds[a].row + HDR + RPAD, nd * 4);
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        const int k = c0 + j - o;
+        v[j] += sg * (long long)(int32_t)__builtin_amdgcn_raw_buffer_load_b32(
+                         rs, k >= 0 ? k * 4 : 0x7ffffff0, 0, 0);
+      }
+    }
+  }
+  bool ovf = false;
+  const int sgn = resolve_c<C>(v, d, &ovf);
+  if (ovf && lane == 0) atomicOr(err, 1u | 64u);
+  return sgn;
+}
+
+// Round the exact sum of a frame and row addends to p bits into the LDS row
+// `out` (div == 0), or divide it by div and round (div >= 1; scratch: 64 CM
+// LDS digits).  Single wavefront.  Returns false on an error (flagged).
+template <int CM>
+__device__ __forceinline__ bool sum_to_row(const long long *frame, bool frame_global,
+                                           const FrameD *fd, int nd, const RowAdd *adds, int nadd,
+                                           int div, int L, int RS, int32_t *scratch, int32_t *out,
+                                           uint32_t *err) {
+  long long lo;
+  int C, ae[3], as[3];
+  const bool okw = sum_window<CM>(fd, nd, adds, nadd, &lo, &C, ae, as, err);
+  bool ok = okw;
+  with_chunks<CM>(C, [&](auto ct) {
+    constexpr int Ct = decltype(ct)::value;
+    int d[Ct];
+    int sgn = 0;
+    if (okw) {
+      sgn = gather_c<Ct>(frame, frame_global, fd, nd, adds, nadd, ae, as, lo, d, err);
+    } else {
+#pragma unroll
+      for (int j = 0; j < Ct; ++j) d[j] = 0;
+    }
+    if (div == 0) ok &= round_to_row<Ct>(d, sgn, lo, false, L, nd, RS, out);
+    else ok &= div_to_row<Ct, CM>(d, sgn, lo, div, L, nd, RS, scratch, out);
+  });
+  return ok;
+}
+
+// Normalised value [sign, E, M] of an LDS row (exact: a row holds p bits).
+// scratch: 64 CM digits of LDS; out: L + 2 words of LDS.  Single wavefront.
+template <int CM>
+__device__ void row_to_norm(const int32_t *row_, int L, int nd, int32_t *scratch_, int32_t *out) {
+  const int lane = lane_id();
+  const l_i32 *row = (const l_i32 *)row_;
+  l_i32 *sc = (l_i32 *)scratch_;
+  const int C = (nd + 1 + 63) >> 6;
+  for (int j = 0; j < C; ++j) {
+    const int k = lane * C + j;
+    const int d = k < nd ? row[HDR + RPAD + k] : 0;
+    sc[k] = d < 0 ? -d : d;
+  }
+  const int sign = row[1];
+  const long long e = row[0];
+  __builtin_amdgcn_wave_barrier();
+  (void)wave_round(scratch_, C, sign, e, false, L, out);
+}
+
+// Copy an LDS row (RS words) to global memory (relaxed: L2-bypassing
+// stores, for rows that other workgroups read).  Single wavefront.
+__device__ __forceinline__ void publish_row(const int32_t *src_, int32_t *dst, int RS, bool relaxed) {
+  const int lane = lane_id();
+  const l_i32 *src = (const l_i32 *)src_;
+  for (int w = lane; w < RS; w += 64) {
+    if (relaxed) st_relaxed(dst + w, src[w]);
+    else ((g_i32 *)dst)[w] = src[w];
+  }
+}
+
 struct Carve {
   long long *lf;       // NFR * WB frame columns
-  long long *tcols;    // 3 task column / digit buffers, 64*CM each
-  int32_t *tq;         // 3 task quotient buffers, 64*CM each
-  int32_t *tnorm;      // 3 tasks x 2 normalised values, NV each
+  long long *tcols;    // 3 task buffers of 64*CM 64-bit words: digits, then quotient digits
+  int32_t *tnorm;      // 3 tasks x 2 normalised values, NV each (aliases trow)
+  int32_t *trow;       // 3 tasks x 2 LDS rows (RS each): a rounded sum, the result
   int32_t *hrow;       // 4 LDS rows (3 Horner accumulators, tau)
   FrameSrc *fs;        // NFR
   FrameD *fd;          // NFR + 1
   int *red;            // 64
+  unsigned long long *tmark;  // phase timer: time of the last mark
   int *span;           // 2 NFR
-  int8_t *offs;        // NFR x maxn per-term digit offsets
-  int maxn;
+  int *hc;             // exponent caches: [3][N+1] coefficient rows, NCONST constants, then
+                       // the constants' nonzero digit ranges (2 NCONST)
+  int8_t *offs;        // adjoint: per-term offset tables of parts without caches
+  int maxn;            // bytes of offs
   int NV;
 };
 
@@ -159,10 +355,9 @@ __device__ Carve carve(unsigned char *smem, const Inst &I) {
   p += (size_t)NFR * I.WB * 8;
   c.tcols = (long long *)p;
   p += (size_t)3 * 64 * I.CM * 8;
-  c.tq = (int32_t *)p;
-  p += (size_t)3 * 64 * I.CM * 4;
   c.tnorm = (int32_t *)p;
-  p += (size_t)6 * NV * 4;
+  c.trow = (int32_t *)p;
+  p += (size_t)6 * (NV > I.RS ? NV : I.RS) * 4;
   c.hrow = (int32_t *)p;
   p += (size_t)4 * I.RS * 4;
   c.fs = (FrameSrc *)p;
@@ -171,19 +366,38 @@ __device__ Carve carve(unsigned char *smem, const Inst &I) {
   p += sizeof(FrameD) * (NFR + 1);
   c.red = (int *)p;
   p += 64 * 4;
+  c.tmark = (unsigned long long *)p;
+  p += 8;
   c.span = (int *)p;
   p += 2 * NFR * 4;
-  c.maxn = max_terms(I.N);
-  c.offs = (int8_t *)p;
+  c.hc = (int *)p;
+  p += ((size_t)3 * (I.N + 1) + 3 * NCONST) * 4;
+  c.maxn = I.mode == MODE_ADJOINT ? adj_table_bytes(I.N) : 0;
+  c.offs = c.maxn ? (int8_t *)p : nullptr;
   return c;
 }
 
-size_t lds_bytes(int L, int N, int RS, int WB, int CM) {
+// Phase timers (thread 0 of the group's first two workgroups, when
+// Inst::prof is set): the ticks since the previous mark go to slot ph.
+// Every workgroup also adds its setup, product, flush and release ticks to
+// its own slots (PROF_RANK words per rank after the first 2 PH_NPHASE).
+__device__ __forceinline__ void prof_mark(const Inst &I, const Carve &cv, int ph) {
+  if (I.prof == nullptr || threadIdx.x != 0) return;
+  const int rank = blockIdx.x - I.wg0;
+  const unsigned long long t = wall_clock64();
+  const unsigned long long dt = t - *cv.tmark;
+  if (rank <= 1) atomicAdd(I.prof + rank * PH_NPHASE + ph, dt);
+  const int slot = ph == PH_SETUP ? 0 : ph == PH_ACCUM ? 1 : ph == PH_FLUSH ? 2 : ph == PH_CLEAR ? 3 : -1;
+  if (slot >= 0) atomicAdd(I.prof + 2 * PH_NPHASE + rank * PROF_RANK + slot, dt);
+  *cv.tmark = t;
+}
+
+size_t lds_bytes(int L, int N, int RS, int WB, int CM, bool adjoint) {
   const int NV = (L + 2 + 3) & ~3;
-  const int maxn = max_terms(N);
-  size_t b = (size_t)NFR * WB * 8 + (size_t)3 * 64 * CM * 8 + (size_t)3 * 64 * CM * 4 +
-             (size_t)6 * NV * 4 + (size_t)4 * RS * 4 + sizeof(FrameSrc) * NFR +
-             sizeof(FrameD) * (NFR + 1) + 64 * 4 + 2 * NFR * 4 + (size_t)maxn;
+  size_t b = (size_t)NFR * WB * 8 + (size_t)3 * 64 * CM * 8 + (size_t)6 * (NV > RS ? NV : RS) * 4 +
+             (size_t)4 * RS * 4 + sizeof(FrameSrc) * NFR + sizeof(FrameD) * (NFR + 1) + 64 * 4 + 8 +
+             2 * NFR * 4 + ((size_t)3 * (N + 1) + 3 * NCONST) * 4 +
+             (adjoint ? (size_t)adj_table_bytes(N) : 0);
   return (b + 255) & ~(size_t)255;
 }
 
@@ -213,6 +427,26 @@ __device__ __forceinline__ void copy_norm(const int32_t *src, int32_t *dst, int 
   }
 }
 
+// Wave 0 of the leader: spin until the NSPLIT arrival counters (one per
+// 128-byte line) sum to at least target; gives up like spin_until.
+__device__ void spin_until_sum(uint32_t *ctr, uint32_t target, uint32_t *err) {
+  const int lane = threadIdx.x & 63;
+  const __amdgpu_buffer_rsrc_t rs = dev_rsrc(ctr, NSPLIT * 128);
+  const int off = lane < NSPLIT ? lane * 128 : 0x7ffffff0;
+  long long polls = 0;
+  while (true) {
+    uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 16);
+#pragma unroll
+    for (int o = 1; o < NSPLIT; o <<= 1) v += __shfl_xor(v, o, 64);
+    if (__shfl(v, 0, 64) >= target) break;
+    __builtin_amdgcn_s_sleep(2);
+    if (++polls > (1LL << 25)) {
+      if (lane == 0) atomicOr(err, 4u);
+      break;
+    }
+  }
+}
+
 // Spin until *flag >= target (thread 0 only); gives up after ~2 s, marking
 // the error word so that the host reports it instead of hanging.
 __device__ void spin_until(uint32_t *flag, uint32_t target, uint32_t *err) {
@@ -230,7 +464,8 @@ __device__ void spin_until(uint32_t *flag, uint32_t target, uint32_t *err) {
 }
 
 // One finalisation task (one wavefront): which = 0 -> beta_{i+1},
-// 1 -> gamma_{i+1}, 2 -> alpha_{i+1}.
+// 1 -> gamma_{i+1}, 2 -> alpha_{i+1}.  Works on rows: the beta task keeps
+// b_i as its previous result row.
 template <int CM>
 __device__ void finalize_task(const Inst &I, const Carve &cv, int which, int i,
                               const long long *frames, bool frames_global, uint32_t *err) {
@@ -244,60 +479,51 @@ __device__ void finalize_task(const Inst &I, const Carve &cv, int which, int i,
       tq = t;
     }
   };
-  const int L = I.L, nd = I.nd, WB = I.WB;
-  long long *cols = cv.tcols + (size_t)which * 64 * I.CM;
-  int32_t *dig = (int32_t *)cols;
-  int32_t *q = cv.tq + (size_t)which * 64 * I.CM;
-  int32_t *tmp = cv.tnorm + (size_t)which * 2 * cv.NV;
-  int32_t *res = tmp + cv.NV;
-  int C;
-  long long dexp;
-  int sgn;
+  const int L = I.L, nd = I.nd, WB = I.WB, RS = I.RS;
+  int32_t *scratch = (int32_t *)(cv.tcols + (size_t)which * 64 * I.CM);
+  int32_t *srow = cv.trow + (size_t)(2 * which) * RS;  // rounded Cauchy sum
+  int32_t *orow = srow + RS;                            // result (beta: b_i before)
   int arr_out;
   bool ok = true;
   if (which == 0 || which == 1) {
     // s1 (which 0) or s2 (which 1): one rounding of the exact Cauchy sum
-    sgn = combine_resolve<CM>(frames + (size_t)which * WB, frames_global, &cv.fd[which], nd, L,
-                              nullptr, 0, dig, &C, &dexp, err);
-    sub(8);
-    ok &= wave_round(dig, C, sgn, dexp, false, L, tmp);
+    ok &= sum_to_row<CM>(frames + (size_t)which * WB, frames_global, &cv.fd[which], nd, nullptr, 0,
+                         0, L, RS, scratch, srow, err);
     sub(9);
-    Addend ad[2];
-    int nad;
-    const FrameD *fr;
-    const long long *fp;
+    RowAdd ad[2];
+    int nad, f;
     if (which == 0) {
-      // R a_i - b_i - s1_i (b_i: this wave's previous result, still in LDS)
-      ad[0] = Addend{res, 0, -1};
-      ad[1] = Addend{tmp, 0, -1};
+      // R a_i - b_i - s1_i
+      ad[0] = RowAdd{orow, -1, 1};
+      ad[1] = RowAdd{srow, -1, 1};
       nad = 2;
-      fr = &cv.fd[3];
-      fp = frames + (size_t)3 * WB;
+      f = 3;
       arr_out = 1;
     } else {
       // s2_i - b g_i
-      ad[0] = Addend{tmp, 0, 1};
+      ad[0] = RowAdd{srow, 1, 1};
       nad = 1;
-      fr = &cv.fd[4];
-      fp = frames + (size_t)4 * WB;
+      f = 4;
       arr_out = 2;
     }
-    sgn = combine_resolve<CM>(fp, frames_global, fr, nd, L, ad, nad, dig, &C, &dexp, err);
-    sub(10);
+    ok &= sum_to_row<CM>(frames + (size_t)f * WB, frames_global, &cv.fd[f], nd, ad, nad, i + 1, L,
+                         RS, scratch, orow, err);
   } else {
     // sigma (b_i - a_i)
-    sgn = combine_resolve<CM>(frames + (size_t)2 * WB, frames_global, &cv.fd[2], nd, L, nullptr,
-                              0, dig, &C, &dexp, err);
+    ok &= sum_to_row<CM>(frames + (size_t)2 * WB, frames_global, &cv.fd[2], nd, nullptr, 0, i + 1,
+                         L, RS, scratch, orow, err);
     arr_out = 0;
   }
-  ok &= wave_div_round<CM>(dig, C, sgn, dexp, i + 1, L, nd, q, res);
   sub(11);
   if (!ok && lane == 0) atomicOr(err, 2u);
-  write_row(res, L, nd, I.RS, row_ptr(I, arr_out, i + 1), I.G > 1, lane, 64);
+  publish_row(orow, row_ptr(I, arr_out, i + 1), RS, I.G > 1);
   sub(12);
-  if (I.coefs)
-    copy_norm(res, I.coefs + ((long long)arr_out * (I.N + 1) + i + 1) * (L + 2), L, false, lane,
+  if (I.coefs) {
+    int32_t *nv = scratch + 64 * I.CM;
+    row_to_norm<CM>(orow, L, nd, scratch, nv);
+    copy_norm(nv, I.coefs + ((long long)arr_out * (I.N + 1) + i + 1) * (L + 2), L, false, lane,
               64);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -315,10 +541,11 @@ __device__ void group_publish(const Inst &I, bool leader, GroupSync &gs, uint32_
     wait_vmem();
     __syncthreads();
     ++gs.gen;
-    if (I.G > 1 && tid == 0) st_relaxed(I.sync + SY_FLAG, gs.gen);
+    if (I.G > 1 && tid < NSPLIT) st_relaxed(I.sync + SY_FLAG + 32 * tid, gs.gen);
   } else {
     ++gs.gen;
-    if (tid == 0) spin_until(I.sync + SY_FLAG, gs.gen, err);
+    const int rank = blockIdx.x - I.wg0;
+    if (tid == 0) spin_until(I.sync + SY_FLAG + 32 * (rank % NSPLIT), gs.gen, err);
     __syncthreads();
   }
 }
@@ -331,11 +558,12 @@ __device__ const long long *group_bulk(const Inst &I, const Carve &cv, int nf, i
                                        GroupSync &gs, uint32_t *err) {
   const int tid = threadIdx.x;
   const int G = I.G, WB = I.WB;
-  // the task buffers are idle during the bulk: they hold the exponent sums
   frame_setup(cv.fs, cv.fd, nf, I.nd, I.RS, cv.red, cv.offs, cv.maxn, (int *)cv.tcols,
               3 * 64 * I.CM * 2, err);
-  frames_accumulate(cv.fs, cv.fd, nf, I.nd, I.RS, WB, cv.lf, rank, G, cv.span, cv.offs, cv.maxn);
+  prof_mark(I, cv, PH_SETUP);
+  frames_accumulate(cv.fs, cv.fd, nf, I.nd, I.RS, WB, cv.lf, rank, G, cv.span);
   __syncthreads();
+  prof_mark(I, cv, PH_ACCUM);
   ++gs.nbulk;
   long long *gf = I.gframes + (size_t)(gs.nbulk & 1) * NFR * WB;
   if (G == 1) return cv.lf;
@@ -352,11 +580,14 @@ __device__ const long long *group_bulk(const Inst &I, const Carve &cv, int nf, i
   }
   wait_vmem();
   __syncthreads();
+  prof_mark(I, cv, PH_FLUSH);
   if (tid == 0)
-    __hip_atomic_fetch_add(I.sync + SY_ARRIVE, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(I.sync + SY_ARRIVE + 32 * (rank % NSPLIT), 1u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
   if (rank == 0) {
-    if (tid == 0) spin_until(I.sync + SY_ARRIVE, (uint32_t)(G * gs.nbulk), err);
+    if (tid < 64) spin_until_sum(I.sync + SY_ARRIVE, (uint32_t)(G * gs.nbulk), err);
     __syncthreads();
+    prof_mark(I, cv, PH_WAIT);
   }
   return gf;
 }
@@ -380,20 +611,63 @@ __device__ void group_release(const Inst &I, const Carve &cv, int nf, bool leade
   group_publish(I, leader, gs, err);
 }
 
+// Exponent cache entries: coefficient row (arr, idx) and constant row c.
+__device__ __forceinline__ int *hc_row(const Inst &I, const Carve &cv, int arr) {
+  return cv.hc + (size_t)arr * (I.N + 1);
+}
+__device__ __forceinline__ int *hc_const(const Inst &I, const Carve &cv, int c) {
+  return cv.hc + (size_t)3 * (I.N + 1) + c;
+}
+__device__ __forceinline__ int *hc_span(const Inst &I, const Carve &cv, int c) {
+  return cv.hc + (size_t)3 * (I.N + 1) + NCONST + 2 * c;
+}
+
+// Digit range [lo, hi] of the row of each constant that holds all its
+// nonzero digits (from the normalised constants; threads 0..NCONST-1).
+__device__ void const_spans(const Inst &I, const Carve &cv) {
+  const int c = threadIdx.x;
+  if (c >= NCONST) return;
+  const g_i32 *nv = (const g_i32 *)(I.cnorm + (size_t)c * (I.L + 2));
+  int *sp = hc_span(I, cv, c);
+  if (nv[0] == 0) {
+    sp[0] = 0;
+    sp[1] = I.nd - 1;
+    return;
+  }
+  int lb = 0;
+  for (int j = 0; j < I.L; ++j) {
+    const uint32_t m = (uint32_t)nv[2 + j];
+    if (m != 0u) {
+      lb = 32 * j + __builtin_ctz(m);
+      break;
+    }
+  }
+  long long shl;
+  (void)floordiv28(nv[1], &shl);  // row digit k = bits [28 k - sh, +28) of M
+  const int sh = (int)shl;
+  sp[0] = (lb + sh) / DBITS;
+  sp[1] = (32 * I.L - 1 + sh) / DBITS;
+}
+
 // Rows 0 of the three coefficient arrays from a normalised state, published
 // to the group; then, once per step, drop cached copies of rows that are
-// about to be rewritten.
-__device__ void start_step(const Inst &I, bool leader, const int32_t *state, GroupSync &gs,
-                           uint32_t *err) {
+// about to be rewritten, and cache the exponents of rows 0 and the constants.
+__device__ void start_step(const Inst &I, const Carve &cv, bool leader, const int32_t *state,
+                           GroupSync &gs, uint32_t *err, bool rows_ready = false) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  if (leader && wave < 3)
-    write_row(state + (size_t)wave * (I.L + 2), I.L, I.nd, I.RS, row_ptr(I, wave, 0), I.G > 1,
-              lane, 64);
-  group_publish(I, leader, gs, err);
+  if (!rows_ready) {
+    if (leader && wave < 3)
+      write_row(state + (size_t)wave * (I.L + 2), I.L, I.nd, I.RS, row_ptr(I, wave, 0), I.G > 1,
+                lane, 64);
+    group_publish(I, leader, gs, err);
+  }
   if (I.G > 1) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     __syncthreads();
   }
+  if (tid < 3) hc_row(I, cv, tid)[0] = row_exp(row_ptr(I, tid, 0));
+  else if (tid < 3 + NCONST) *hc_const(I, cv, tid - 3) = row_exp(I.consts + (size_t)(tid - 3) * I.RS);
+  __syncthreads();
 }
 
 // The Taylor coefficients 1..N of one step (equation (3)), rows 0 given.
@@ -403,23 +677,45 @@ __device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, G
   const int tid = threadIdx.x, wave = tid >> 6;
   const bool leader = rank == 0;
   const int RS = I.RS;
-  // the beta task keeps b_i in LDS (its result slot): start with b_0
-  if (leader && wave == 0)
-    copy_norm(state + (I.L + 2), cv.tnorm + cv.NV, I.L, false, threadIdx.x & 63, 64);
+  // the beta task keeps b_i in LDS (its result row): start with the row b_0
+  if (leader && wave == 0) {
+    const g_i32 *b0 = (const g_i32 *)row_ptr(I, 1, 0);
+    l_i32 *dst = (l_i32 *)(cv.trow + RS);
+    for (int w = threadIdx.x & 63; w < RS; w += 64) dst[w] = b0[w];
+  }
+  (void)state;
   for (int i = 0; i < I.N; ++i) {
     if (tid == 0) {
       FrameSrc *fs = cv.fs;
-      fs[0] = mk_frame1(mk_part(PK_CAUCHY, i + 1, i, row_ptr(I, 0, 0), row_ptr(I, 2, 0)));
-      fs[1] = mk_frame1(mk_part(PK_CAUCHY, i + 1, i, row_ptr(I, 0, 0), row_ptr(I, 1, 0)));
-      fs[2] = mk_frame2(mk_part(PK_ONE, 1, 0, I.consts + (size_t)C_SIGMA * RS, row_ptr(I, 1, i)),
-                        mk_part(PK_ONE, 1, 0, I.consts + (size_t)C_NSIGMA * RS, row_ptr(I, 0, i)));
-      fs[3] = mk_frame1(mk_part(PK_ONE, 1, 0, I.consts + (size_t)C_R * RS, row_ptr(I, 0, i)));
-      fs[4] = mk_frame1(mk_part(PK_ONE, 1, 0, I.consts + (size_t)C_NB * RS, row_ptr(I, 2, i)));
+      const int *ha = hc_row(I, cv, 0), *hb = hc_row(I, cv, 1), *hg = hc_row(I, cv, 2);
+      auto cst = [&](int c) { return I.consts + (size_t)c * RS; };
+      fs[0] = mk_frame1(mk_part(PK_CAUCHY, i + 1, i, row_ptr(I, 0, 0), row_ptr(I, 2, 0), ha, hg));
+      fs[1] = mk_frame1(mk_part(PK_CAUCHY, i + 1, i, row_ptr(I, 0, 0), row_ptr(I, 1, 0), ha, hb));
+      fs[2] = mk_frame2(mk_part(PK_ONE, 1, 0, cst(C_SIGMA), row_ptr(I, 1, i),
+                                hc_const(I, cv, C_SIGMA), hb + i),
+                        mk_part(PK_ONE, 1, 0, cst(C_NSIGMA), row_ptr(I, 0, i),
+                                hc_const(I, cv, C_NSIGMA), ha + i));
+      fs[3] = mk_frame1(mk_part(PK_ONE, 1, 0, cst(C_R), row_ptr(I, 0, i), hc_const(I, cv, C_R),
+                                ha + i));
+      // sigma and R are often short: only their nonzero digit rows take tiles
+      fs[2].mlo = min(hc_span(I, cv, C_SIGMA)[0], hc_span(I, cv, C_NSIGMA)[0]);
+      fs[2].mhi = max(hc_span(I, cv, C_SIGMA)[1], hc_span(I, cv, C_NSIGMA)[1]);
+      fs[3].mlo = hc_span(I, cv, C_R)[0];
+      fs[3].mhi = hc_span(I, cv, C_R)[1];
+      fs[4] = mk_frame1(mk_part(PK_ONE, 1, 0, cst(C_NB), row_ptr(I, 2, i), hc_const(I, cv, C_NB),
+                                hg + i));
     }
     __syncthreads();
     const long long *frames = group_bulk(I, cv, NFR, rank, gs, err);
     if (leader && wave < 3) finalize_task<CM>(I, cv, wave, i, frames, I.G > 1, err);
+    if (leader) {
+      __syncthreads();
+      prof_mark(I, cv, PH_FINAL);
+    }
     group_release(I, cv, NFR, leader, frames, gs, err);
+    prof_mark(I, cv, PH_CLEAR);
+    // the new rows are published: cache their exponents
+    if (tid < 3) hc_row(I, cv, tid)[i + 1] = row_exp(row_ptr(I, tid, i + 1));
   }
 }
 
@@ -429,40 +725,50 @@ __device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, G
 // equation (2) (addend: coefficient rows) and for the adjoint's powers of tau
 // (no addend; each result row is also stored to out rows).
 template <int CM>
-__device__ void tau_chains(const Inst &I, const Carve &cv, int count, int mode, uint32_t *err) {
+__device__ __noinline__ void tau_chains(const Inst &I, const Carve &cv, int count, int mode,
+                                        uint32_t *err,
+                           int c0 = 0, int nc = 3) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int L = I.L, nd = I.nd, RS = I.RS, WB = I.WB, N = I.N;
   const int32_t *tau_lds = cv.hrow + (size_t)3 * RS;
+  const bool timed = I.prof != nullptr && tid == 0 && blockIdx.x == I.wg0;
+  unsigned long long tq = timed ? wall_clock64() : 0;
+  auto sub = [&](int slot) {
+    if (timed) {
+      unsigned long long t = wall_clock64();
+      atomicAdd(I.prof + slot, t - tq);
+      tq = t;
+    }
+  };
   for (int it = 0; it < count; ++it) {
     if (tid == 0) {
-      for (int c = 0; c < 3; ++c)
-        cv.fs[c] = mk_frame1(mk_part(PK_ONE, 1, 0, tau_lds, cv.hrow + (size_t)c * RS));
-      frame_setup_single(cv.fs, cv.fd, 3, nd, cv.offs, cv.maxn);
+      for (int f = 0; f < nc; ++f)
+        cv.fs[f] = mk_frame1(mk_part(PK_ONE, 1, 0, tau_lds, cv.hrow + (size_t)(c0 + f) * RS));
+      frame_setup_single(cv.fs, cv.fd, nc, nd, RS);
     }
     __syncthreads();
-    frames_accumulate(cv.fs, cv.fd, 3, nd, RS, WB, cv.lf, 0, 1, cv.span, cv.offs, cv.maxn);
+    lds_products(cv.fs, cv.fd, nc, nd, WB, cv.lf);
     __syncthreads();
-    if (wave < 3) {
-      int32_t *dig = (int32_t *)(cv.tcols + (size_t)wave * 64 * I.CM);
-      int32_t *h = cv.tnorm + (size_t)wave * 2 * cv.NV;
-      Addend ad;
+    sub(13);
+    if (wave < nc) {
+      const int c = c0 + wave;  // chain of this wavefront; frame `wave`
+      RowAdd ad;
       int nad = 0;
       if (mode == 0) {  // Horner: i = N-1-it
-        ad = Addend{row_ptr(I, wave, N - 1 - it), 1, 1};
+        ad = RowAdd{row_ptr(I, c, N - 1 - it), 1, 0};
         nad = 1;
       }
-      int C;
-      long long dexp;
-      int sgn = combine_resolve<CM>(cv.lf + (size_t)wave * WB, false, &cv.fd[wave], nd, L, &ad,
-                                    nad, dig, &C, &dexp, err);
-      bool ok = wave_round(dig, C, sgn, dexp, false, L, h);
+      int32_t *h = cv.hrow + (size_t)c * RS;
+      int32_t *scratch = (int32_t *)(cv.tcols + (size_t)wave * 64 * I.CM);
+      bool ok = sum_to_row<CM>(cv.lf + (size_t)wave * WB, false, &cv.fd[wave], nd, &ad, nad, 0, L,
+                               RS, scratch, h, err);
       if (!ok && lane == 0) atomicOr(err, 2u);
-      write_row(h, L, nd, RS, cv.hrow + (size_t)wave * RS, false, lane, 64);
-      if (mode == 1) write_row(h, L, nd, RS, q_row(I, wave, it + 1), I.G > 1, lane, 64);
-      int nc = cv.fd[wave].nz ? frame_cols(cv.fd[wave], nd) : 0;
-      for (int c = lane; c < nc; c += 64) cv.lf[(size_t)wave * WB + c] = 0;
+      if (mode == 1) publish_row(h, q_row(I, c, it + 1), RS, I.G > 1);
+      int ncol = cv.fd[wave].nz ? frame_cols(cv.fd[wave], nd) : 0;
+      for (int q = lane; q < ncol; q += 64) ((l_i64 *)cv.lf)[(size_t)wave * WB + q] = 0;
     }
     __syncthreads();
+    sub(15);
   }
 }
 
@@ -479,16 +785,16 @@ __global__ void __launch_bounds__(WGS) k_run(const Inst *__restrict__ insts,
   Carve cv = carve(smem, I);
   for (int j = tid; j < NFR * WB; j += WGS) cv.lf[j] = 0;
   GroupSync gs{0u, 0ull};
-  const bool timed = I.prof != nullptr && tid == 0 && (rank == 0 || rank == 1);
-  unsigned long long *prof = timed ? I.prof + (rank == 0 ? 0 : PH_NPHASE) : nullptr;
-  unsigned long long tp = timed ? wall_clock64() : 0;
-  auto mark = [&](int phase) {
-    if (timed) {
-      unsigned long long t = wall_clock64();
-      atomicAdd(prof + phase, t - tp);
-      tp = t;
+  const_spans(I, cv);
+  if (tid == 0) {
+    *cv.tmark = wall_clock64();
+    if (I.prof) {
+      // where this workgroup runs: XCC and hardware id registers
+      unsigned long long *pr = I.prof + 2 * PH_NPHASE + rank * PROF_RANK;
+      pr[4] = (unsigned)__builtin_amdgcn_s_getreg((3 << 11) | 20);
+      pr[5] = (unsigned)__builtin_amdgcn_s_getreg((31 << 11) | 4);
     }
-  };
+  }
   if (leader) {
     for (int c = wave; c < NCONST; c += 4)
       write_row(I.cnorm + (size_t)c * (L + 2), L, nd, RS, I.consts + (size_t)c * RS, G > 1, lane,
@@ -502,13 +808,42 @@ __global__ void __launch_bounds__(WGS) k_run(const Inst *__restrict__ insts,
       if (step == 0 && I.ckpt) copy_norm(sv, I.ckpt + (size_t)wave * (L + 2), L, false, lane, 64);
       if (I.coefs) copy_norm(sv, I.coefs + (size_t)wave * (N + 1) * (L + 2), L, false, lane, 64);
     }
-    start_step(I, leader, I.state, gs, err);
-    mark(PH_STEP0);
+    // with three or more workgroups the Horner chains of the previous step
+    // have already written rows 0
+    start_step(I, cv, leader, I.state, gs, err, G >= 3 && step > 0);
+    prof_mark(I, cv, PH_STEP0);
     forward_coefficients<CM>(I, cv, rank, gs, I.state, err);
-    mark(PH_ACCUM);
     if (I.mode == MODE_COEFFS) break;
-    // Horner: h = c_N; h <- round(h tau + c_i), i = N-1..0, three chains at once
-    if (leader) {
+    // Horner (equation (2)): h = c_N; h <- round(h tau + c_i), i = N-1..0
+    if (G >= 3) {
+      // chain c on workgroup c; it writes row 0 of the next step and the state
+      if (rank < 3) {
+        const int c = rank;
+        int32_t *h = cv.hrow + (size_t)c * RS;
+        for (int j = tid; j < RS; j += WGS) {
+          h[j] = row_ptr(I, c, N)[j];
+          cv.hrow[(size_t)3 * RS + j] = (I.consts + (size_t)C_TAU * RS)[j];
+        }
+        __syncthreads();
+        tau_chains<CM>(I, cv, N, 0, err, c, 1);
+        if (wave == 0) {
+          publish_row(h, row_ptr(I, c, 0), RS, true);
+          int32_t *scratch = (int32_t *)cv.tcols;
+          int32_t *hn = scratch + 64 * I.CM;
+          row_to_norm<CM>(h, L, nd, scratch, hn);
+          copy_norm(hn, I.state + (size_t)c * (L + 2), L, true, lane, 64);
+          if (I.ckpt)
+            copy_norm(hn, I.ckpt + ((size_t)(step + 1) * 3 + c) * (L + 2), L, true, lane, 64);
+        }
+        wait_vmem();
+        __syncthreads();
+        if (tid == 0)
+          __hip_atomic_fetch_add(I.sync + SY_HDONE, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (tid == 0) spin_until(I.sync + SY_HDONE, (uint32_t)(3 * (step + 1)), err);
+      __syncthreads();
+      prof_mark(I, cv, PH_HORNER);
+    } else if (leader) {
       for (int j = tid; j < 4 * RS; j += WGS) {
         int c = j / RS, w = j - c * RS;
         cv.hrow[j] = c < 3 ? row_ptr(I, c, N)[w] : (I.consts + (size_t)C_TAU * RS)[w];
@@ -516,13 +851,15 @@ __global__ void __launch_bounds__(WGS) k_run(const Inst *__restrict__ insts,
       __syncthreads();
       tau_chains<CM>(I, cv, N, 0, err);
       if (wave < 3) {
-        const int32_t *h = cv.tnorm + (size_t)wave * 2 * cv.NV;
+        int32_t *scratch = (int32_t *)(cv.tcols + (size_t)wave * 64 * I.CM);
+        int32_t *h = scratch + 64 * I.CM;
+        row_to_norm<CM>(cv.hrow + (size_t)wave * RS, L, nd, scratch, h);
         copy_norm(h, I.state + (size_t)wave * (L + 2), L, false, lane, 64);
         if (I.ckpt)
           copy_norm(h, I.ckpt + ((size_t)(step + 1) * 3 + wave) * (L + 2), L, false, lane, 64);
       }
       __syncthreads();
-      mark(PH_HORNER);
+      prof_mark(I, cv, PH_HORNER);
     }
   }
 }
@@ -560,6 +897,8 @@ __global__ void __launch_bounds__(WGS) k_adj(const Inst *__restrict__ insts,
   for (int j = tid; j < NFR * WB; j += WGS) cv.lf[j] = 0;
   GroupSync gs{0u, 0ull};
   const bool rel = G > 1;
+  const_spans(I, cv);
+  if (tid == 0) *cv.tmark = wall_clock64();
   if (leader) {
     for (int c = wave; c < NCONST; c += 4)
       write_row(I.cnorm + (size_t)c * (L + 2), L, nd, RS, I.consts + (size_t)c * RS, rel, lane, 64);
@@ -576,7 +915,7 @@ __global__ void __launch_bounds__(WGS) k_adj(const Inst *__restrict__ insts,
   const int32_t *cs = I.consts;
   for (long long n = I.nsteps - 1; n >= 0; --n) {
     // 1. the step's coefficients from its checkpoint
-    start_step(I, leader, I.ckpt + (size_t)n * 3 * (L + 2), gs, err);
+    start_step(I, cv, leader, I.ckpt + (size_t)n * 3 * (L + 2), gs, err);
     forward_coefficients<CM>(I, cv, rank, gs, I.ckpt + (size_t)n * 3 * (L + 2), err);
     // 2. q^c_0 = incoming adjoint, q^c_i = round(q^c_{i-1} tau)
     if (leader) {
@@ -597,27 +936,35 @@ __global__ void __launch_bounds__(WGS) k_adj(const Inst *__restrict__ insts,
         const int one = m < N ? 1 : 0;
         const int mi = m < N ? m : 0;
         FrameSrc *fs = cv.fs;
-        fs[0] = mk_frame4(mk_part(PK_CORR, k, m, adj_row(I, A_NV, 0), row_ptr(I, 2, 0)),
-                          mk_part(PK_CORR, k, m, adj_row(I, A_W, 0), row_ptr(I, 1, 0)),
-                          mk_part(PK_ONE, one, 0, cs + (size_t)C_NSIGMA * RS, adj_row(I, A_U, mi)),
-                          mk_part(PK_ONE, one, 0, cs + (size_t)C_R * RS, adj_row(I, A_V, mi)));
-        fs[1] = mk_frame2(mk_part(PK_CORR, k, m, adj_row(I, A_W, 0), row_ptr(I, 0, 0)),
-                          mk_part(PK_ONE, one, 0, cs + (size_t)C_SIGMA * RS, adj_row(I, A_U, mi)));
-        fs[2] = mk_frame2(mk_part(PK_CORR, k, m, adj_row(I, A_NV, 0), row_ptr(I, 0, 0)),
-                          mk_part(PK_ONE, one, 0, cs + (size_t)C_NB * RS, adj_row(I, A_W, mi)));
+        const int *ha = hc_row(I, cv, 0), *hb = hc_row(I, cv, 1), *hg = hc_row(I, cv, 2);
+        fs[0] = mk_frame4(
+            mk_part(PK_CORR, k, m, adj_row(I, A_NV, 0), row_ptr(I, 2, 0), nullptr, hg),
+            mk_part(PK_CORR, k, m, adj_row(I, A_W, 0), row_ptr(I, 1, 0), nullptr, hb),
+            mk_part(PK_ONE, one, 0, cs + (size_t)C_NSIGMA * RS, adj_row(I, A_U, mi),
+                    hc_const(I, cv, C_NSIGMA), nullptr),
+            mk_part(PK_ONE, one, 0, cs + (size_t)C_R * RS, adj_row(I, A_V, mi),
+                    hc_const(I, cv, C_R), nullptr));
+        fs[1] = mk_frame2(
+            mk_part(PK_CORR, k, m, adj_row(I, A_W, 0), row_ptr(I, 0, 0), nullptr, ha),
+            mk_part(PK_ONE, one, 0, cs + (size_t)C_SIGMA * RS, adj_row(I, A_U, mi),
+                    hc_const(I, cv, C_SIGMA), nullptr));
+        fs[2] = mk_frame2(
+            mk_part(PK_CORR, k, m, adj_row(I, A_NV, 0), row_ptr(I, 0, 0), nullptr, ha),
+            mk_part(PK_ONE, one, 0, cs + (size_t)C_NB * RS, adj_row(I, A_W, mi),
+                    hc_const(I, cv, C_NB), nullptr));
       }
       __syncthreads();
       const long long *frames = group_bulk(I, cv, 3, rank, gs, err);
       if (leader && wave < 3) {
         int32_t *dig = (int32_t *)(cv.tcols + (size_t)wave * 64 * I.CM);
-        int32_t *q = cv.tq + (size_t)wave * 64 * I.CM;
+        int32_t *q = dig + 64 * I.CM;
         int32_t *res = cv.tnorm + (size_t)wave * 2 * cv.NV;
         int32_t *out = res + cv.NV;
         Addend ad[2];
         int nad = 1;
-        ad[0] = Addend{q_row(I, wave, m), 1, 1};
+        ad[0] = Addend{q_row(I, wave, m), 1, 1, 0};
         if (wave == 1 && m < N) {
-          ad[1] = Addend{adj_row(I, A_NV, m), 1, 1};
+          ad[1] = Addend{adj_row(I, A_NV, m), 1, 1, 0};
           nad = 2;
         }
         int C;
@@ -626,7 +973,7 @@ __global__ void __launch_bounds__(WGS) k_adj(const Inst *__restrict__ insts,
                                       dig, &C, &dexp, err);
         bool ok = wave_round(dig, C, sgn, dexp, false, L, res);
         if (m > 0) {
-          Addend a1 = Addend{res, 0, 1};
+          Addend a1 = Addend{res, 0, 1, 1};
           sgn = combine_resolve<CM>(nullptr, false, nullptr, nd, L, &a1, 1, dig, &C, &dexp, err);
           ok &= wave_div_round<CM>(dig, C, sgn, dexp, m, L, nd, q, out);
           // wave 0 -> u, 1 -> v, 2 -> w, with their negations
@@ -642,17 +989,18 @@ __global__ void __launch_bounds__(WGS) k_adj(const Inst *__restrict__ insts,
     // 4. parameter derivatives of this step, one rounded add each
     if (tid == 0) {
       FrameSrc *fs = cv.fs;
-      fs[0] = mk_frame2(mk_part(PK_DOT, N, 0, adj_row(I, A_U, 0), row_ptr(I, 1, 0)),
-                        mk_part(PK_DOT, N, 0, adj_row(I, A_NU, 0), row_ptr(I, 0, 0)));
-      fs[1] = mk_frame1(mk_part(PK_DOT, N, 0, adj_row(I, A_V, 0), row_ptr(I, 0, 0)));
-      fs[2] = mk_frame1(mk_part(PK_DOT, N, 0, adj_row(I, A_NW, 0), row_ptr(I, 2, 0)));
+      const int *ha = hc_row(I, cv, 0), *hb = hc_row(I, cv, 1), *hg = hc_row(I, cv, 2);
+      fs[0] = mk_frame2(mk_part(PK_DOT, N, 0, adj_row(I, A_U, 0), row_ptr(I, 1, 0), nullptr, hb),
+                        mk_part(PK_DOT, N, 0, adj_row(I, A_NU, 0), row_ptr(I, 0, 0), nullptr, ha));
+      fs[1] = mk_frame1(mk_part(PK_DOT, N, 0, adj_row(I, A_V, 0), row_ptr(I, 0, 0), nullptr, ha));
+      fs[2] = mk_frame1(mk_part(PK_DOT, N, 0, adj_row(I, A_NW, 0), row_ptr(I, 2, 0), nullptr, hg));
     }
     __syncthreads();
     const long long *frames = group_bulk(I, cv, 3, rank, gs, err);
     if (leader && wave < 3) {
       int32_t *dig = (int32_t *)(cv.tcols + (size_t)wave * 64 * I.CM);
       int32_t *res = cv.tnorm + (size_t)wave * 2 * cv.NV;
-      Addend ad = Addend{bar_ptr(I, 3 + wave), 0, 1};
+      Addend ad = Addend{bar_ptr(I, 3 + wave), 0, 1, 0};
       int C;
       long long dexp;
       int sgn = combine_resolve<CM>(frames + (size_t)wave * WB, rel, &cv.fd[wave], nd, L, &ad, 1,
@@ -738,20 +1086,17 @@ hipError_t launch_adj(const Inst *d_insts, const int *d_wg_inst, int nwg, int CM
 }
 
 template <int CM>
-static hipError_t set_lds_cm(size_t lds) {
-  hipError_t e = hipFuncSetAttribute((const void *)k_run<CM>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void *)k_adj<CM>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)lds);
+static hipError_t set_lds_cm(size_t lds, bool adjoint) {
+  const void *k = adjoint ? (const void *)k_adj<CM> : (const void *)k_run<CM>;
+  return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-hipError_t set_kernel_lds(int CM, size_t lds) {
+hipError_t set_kernel_lds(int CM, size_t lds, bool adjoint) {
   switch (CM) {
-    case 4: return set_lds_cm<4>(lds);
-    case 8: return set_lds_cm<8>(lds);
-    case 16: return set_lds_cm<16>(lds);
-    case 32: return set_lds_cm<32>(lds);
+    case 4: return set_lds_cm<4>(lds, adjoint);
+    case 8: return set_lds_cm<8>(lds, adjoint);
+    case 16: return set_lds_cm<16>(lds, adjoint);
+    case 32: return set_lds_cm<32>(lds, adjoint);
     default: return hipErrorInvalidValue;
   }
 }
@@ -765,39 +1110,32 @@ hipError_t launch_clear(void *p, size_t bytes, hipStream_t s) {
   return hipGetLastError();
 }
 
-int max_coresident(int CM, size_t lds, int *out) {
+template <int CM>
+static hipError_t occupancy_cm(int *nb, size_t lds, bool adjoint) {
+  if (adjoint) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_adj<CM>, WGS, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_run<CM>, WGS, lds);
+}
+
+int max_coresident(int CM, size_t lds, int *out, bool adjoint) {
   int nb = 0;
-  // the occupancy query honours the kernels' dynamic-LDS limit: raise it first
-  hipError_t e = set_kernel_lds(CM, lds);
+  // the occupancy query honours the kernel's dynamic-LDS limit: raise it first
+  hipError_t e = set_kernel_lds(CM, lds, adjoint);
   if (e != hipSuccess) {
     (void)hipGetLastError();  // do not leave the failure for the next launch to report
     return -1;
   }
-  int na = 0;
   switch (CM) {
-    case 4:
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_run<4>, WGS, lds);
-      if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&na, k_adj<4>, WGS, lds);
-      break;
-    case 8:
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_run<8>, WGS, lds);
-      if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&na, k_adj<8>, WGS, lds);
-      break;
-    case 16:
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_run<16>, WGS, lds);
-      if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&na, k_adj<16>, WGS, lds);
-      break;
-    case 32:
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_run<32>, WGS, lds);
-      if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&na, k_adj<32>, WGS, lds);
-      break;
+    case 4: e = occupancy_cm<4>(&nb, lds, adjoint); break;
+    case 8: e = occupancy_cm<8>(&nb, lds, adjoint); break;
+    case 16: e = occupancy_cm<16>(&nb, lds, adjoint); break;
+    case 32: e = occupancy_cm<32>(&nb, lds, adjoint); break;
     default: return -1;
   }
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return -2;
   }
-  *out = nb < na ? nb : na;
+  *out = nb;
   return 0;
 }
 

@@ -55,6 +55,23 @@ __device__ __forceinline__ uint32_t mant_bits28(const int32_t *M, int L, long lo
   return (uint32_t)(w & (unsigned long long)DMASK);
 }
 
+// The same on mantissas in LDS or global memory, with int bit positions.
+template <typename P>
+__device__ __forceinline__ uint32_t mant_bits28_as(P M, int L, int b) {
+  const int q = b >= 0 ? (b >> 5) : -((-b + 31) >> 5);
+  const int r = b - q * 32;
+  unsigned long long lo = (q >= 0 && q < L) ? (uint32_t)M[q] : 0u;
+  unsigned long long hi = (q + 1 >= 0 && q + 1 < L) ? (uint32_t)M[q + 1] : 0u;
+  unsigned long long w = ((hi << 32) | lo) >> r;
+  return (uint32_t)(w & (unsigned long long)DMASK);
+}
+__device__ __forceinline__ uint32_t mant_bits28_l(const l_i32 *M, int L, int b) {
+  return mant_bits28_as(M, L, b);
+}
+__device__ __forceinline__ uint32_t mant_bits28_g(const g_i32 *M, int L, int b) {
+  return mant_bits28_as(M, L, b);
+}
+
 // Row of a normalised value nv = [sign, E, M[L]]: digit exponent e =
 // floor(E / 28), digits of M * 2^(E - 28 e) with the sign applied.  Written
 // by one wavefront (or any group of `nthr` threads indexed by `tid`), header
@@ -102,51 +119,62 @@ enum { PK_CAUCHY = 0, PK_CORR = 1, PK_DOT = 2, PK_ONE = 3 };
 struct FramePart {
   int kind, n, idx, pad;
   const int32_t *U, *V;
+  // optional exponent caches (LDS) indexed like the rows (row j of U ->
+  // hU[j]): the row's digit exponent, or HZ for a zero row
+  const int *hU, *hV;
+  // parts without both caches: per-term digit offsets in LDS (frame_setup)
+  const int8_t *ot;
 };
 
 struct FrameSrc {
   int nparts, n;  // n = total terms
+  int mlo, mhi;   // digit range holding every nonzero digit of the parts' U rows
   FramePart p[4];
 };
 
 struct FrameD {
-  int n, base, S, NT, nz, obase;  // obase: first entry of this frame's offset slice
-  long long cost0;                // first cost unit of this frame
+  int n, base, S, NT, nz, mt0, MTf, pad;  // tile rows mt0 .. mt0 + MTf - 1 can be nonzero
 };
+
+typedef __attribute__((address_space(3))) FrameSrc l_FrameSrc;
+typedef __attribute__((address_space(3))) FrameD l_FrameD;
+
+constexpr int HZ = (int)0x80000000;  // exponent cache entry of a zero row
+
+__device__ __forceinline__ int row_exp(const int32_t *row) { return row[1] != 0 ? row[0] : HZ; }
+
+__device__ __forceinline__ void part_rows(const FramePart &q, int k, int *iu, int *iv) {
+  switch (q.kind) {
+    case PK_CAUCHY: *iu = q.idx - k; *iv = k; break;
+    case PK_CORR: *iu = q.idx + k; *iv = k; break;
+    case PK_DOT: *iu = k; *iv = k; break;
+    default: *iu = 0; *iv = 0;
+  }
+}
 
 __device__ __forceinline__ void part_term(const FramePart &q, int k, int RS, const int32_t **U,
                                           const int32_t **V) {
-  switch (q.kind) {
-    case PK_CAUCHY:
-      *U = q.U + (long long)(q.idx - k) * RS;
-      *V = q.V + (long long)k * RS;
-      break;
-    case PK_CORR:
-      *U = q.U + (long long)(q.idx + k) * RS;
-      *V = q.V + (long long)k * RS;
-      break;
-    case PK_DOT:
-      *U = q.U + (long long)k * RS;
-      *V = q.V + (long long)k * RS;
-      break;
-    default:
-      *U = q.U;
-      *V = q.V;
-  }
+  int iu, iv;
+  part_rows(q, k, &iu, &iv);
+  *U = q.U + (long long)iu * RS;
+  *V = q.V + (long long)iv * RS;
 }
 
-__device__ __forceinline__ void frame_term(const FrameSrc &f, int k, int RS, const int32_t **U,
-                                           const int32_t **V) {
-  int j = 0;
-  while (j + 1 < f.nparts && k >= f.p[j].n) {
-    k -= f.p[j].n;
-    ++j;
-  }
-  part_term(f.p[j], k, RS, U, V);
+__device__ __forceinline__ int row_exp_g(const g_i32 *row) { return row[1] != 0 ? row[0] : HZ; }
+
+// Exponent sum of term k of a part (HZ when either row is zero).  The rows
+// are in global memory, the caches in LDS.
+__device__ __forceinline__ int part_esum(const FramePart &q, int k, int RS) {
+  int iu, iv;
+  part_rows(q, k, &iu, &iv);
+  const int eu = q.hU ? ((const l_i32 *)q.hU)[iu] : row_exp_g((const g_i32 *)q.U + iu * RS);
+  const int ev = q.hV ? ((const l_i32 *)q.hV)[iv] : row_exp_g((const g_i32 *)q.V + iv * RS);
+  return (eu == HZ || ev == HZ) ? HZ : eu + ev;
 }
 
 __host__ __device__ inline FramePart mk_part(int kind, int n, int idx, const int32_t *U,
-                                             const int32_t *V) {
+                                             const int32_t *V, const int *hU = nullptr,
+                                             const int *hV = nullptr) {
   FramePart q;
   q.kind = kind;
   q.n = n;
@@ -154,6 +182,9 @@ __host__ __device__ inline FramePart mk_part(int kind, int n, int idx, const int
   q.pad = 0;
   q.U = U;
   q.V = V;
+  q.hU = hU;
+  q.hV = hV;
+  q.ot = nullptr;
   return q;
 }
 
@@ -161,6 +192,8 @@ __host__ __device__ inline FrameSrc mk_frame1(FramePart a) {
   FrameSrc f;
   f.nparts = 1;
   f.n = a.n;
+  f.mlo = 0;
+  f.mhi = 0x7fffffff;
   f.p[0] = a;
   f.p[1] = a;
   f.p[2] = a;
@@ -232,36 +265,37 @@ __device__ __forceinline__ void tile_normalize(long long (&acc)[16]) {
 }
 
 // Per-workgroup frame setup: exponent base and spread of each frame's
-// nonzero terms (one workgroup reduction for all frames), and the table of
-// per-term digit offsets offs[obase_f + k] (0 for zero terms, whose rows
-// are all-zero digits).  Every thread of the workgroup calls this.
-// red: 4 waves x 2 NFR ints.
-__device__ void frame_setup(const FrameSrc *fs, FrameD *fd, int nf, int nd, int RS, int *red,
+// nonzero terms (one workgroup reduction for all frames).  Exponents come
+// from the parts' caches (LDS) or, for parts without both caches, from the
+// row headers; those parts get a table of per-term digit offsets in LDS
+// (offs, maxn bytes; esum: int scratch of esum_cap entries), so that the
+// product loop never waits on a header load.  Every thread of the
+// workgroup calls this; thread 0 stores the table slices into fs.
+__device__ void frame_setup(FrameSrc *fs, FrameD *fd, int nf, int nd, int RS, int *red,
                             int8_t *offs, int maxn, int *esum, int esum_cap, uint32_t *err) {
   const int tid = threadIdx.x;
-  const int MT = (nd + TQ - 1) / TQ;
   int mn[NFR], mx[NFR];
-  // one pass over the row headers: exponent sums kept in LDS (esum, laid
-  // out frame after frame; INT_MIN marks a zero term) for the offset pass
-  int eb = 0;
+  int ob = 0;  // table position of the next uncached part (same in every thread)
+  bool fits = true;
 #pragma unroll
   for (int f = 0; f < NFR; ++f) {
     mn[f] = 0x7fffffff;
     mx[f] = -0x7fffffff;
     if (f < nf) {
-      const bool keep = eb + fs[f].n <= esum_cap;
-      for (int k = tid; k < fs[f].n; k += WGS) {
-        const int32_t *U, *V;
-        frame_term(fs[f], k, RS, &U, &V);
-        int e = (int)0x80000000;
-        if (U[1] != 0 && V[1] != 0) {
-          e = U[0] + V[0];
-          mn[f] = min(mn[f], e);
-          mx[f] = max(mx[f], e);
+      for (int j = 0; j < fs[f].nparts; ++j) {
+        const FramePart &q = fs[f].p[j];
+        const bool cached = q.hU && q.hV;
+        if (!cached && (ob + q.n > maxn || ob + q.n > esum_cap)) fits = false;
+        for (int k = tid; k < q.n; k += WGS) {
+          const int e = part_esum(q, k, RS);
+          if (!cached && fits) ((l_i32 *)esum)[ob + k] = e;
+          if (e != HZ) {
+            mn[f] = min(mn[f], e);
+            mx[f] = max(mx[f], e);
+          }
         }
-        if (keep) esum[eb + k] = e;
+        if (!cached) ob += (q.n + 15) & ~15;
       }
-      eb += fs[f].n;
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -287,79 +321,57 @@ __device__ void frame_setup(const FrameSrc *fs, FrameD *fd, int nf, int nd, int 
     d.base = d.nz ? a : 0;
     int S = d.nz ? (b - a) : 0;
     if (S > SMAX) {
-      atomicOr(err, 1u);
+      atomicOr(err, 1u | 16u);
       S = SMAX;
     }
     d.S = S;
     d.NT = (nd + S + TQ - 1) / TQ;
-    d.obase = 0;
+    const int MT = (nd + TQ - 1) / TQ;
+    const int m0 = max(fs[f].mlo, 0) / TQ;
+    const int m1 = min(fs[f].mhi, nd - 1) / TQ;
+    d.mt0 = m0 < MT ? m0 : 0;
+    d.MTf = m1 >= m0 && m0 < MT ? min(m1, MT - 1) - m0 + 1 : MT;
+    d.pad = 0;
     fd[f] = d;
   }
+  if (tid == 0 && !fits) atomicOr(err, 8u);  // table too small: never expected
   __syncthreads();
-  if (tid == 0) {
-    long long c = 0;
-    int ob = 0;
-    for (int f = 0; f < nf; ++f) {
-      fd[f].cost0 = c;
-      if (fd[f].nz) c += (long long)MT * fd[f].NT * fd[f].n;
-      fd[f].obase = ob;
-      ob += (fs[f].n + 15) & ~15;
-    }
-    fd[nf].cost0 = c;
-    if (ob > maxn) {  // cannot happen for the frames built here; never write past the table
-      atomicOr(err, 1u);
-      for (int f = 0; f <= nf; ++f) fd[f].cost0 = 0;
-    }
-  }
-  __syncthreads();
-  eb = 0;
+  if (ob == 0 || !fits) return;
+  ob = 0;
   for (int f = 0; f < nf; ++f) {
     const int base = fd[f].base, S = fd[f].S;
-    const bool keep = eb + fs[f].n <= esum_cap;
-    if (fd[f].obase + fs[f].n <= maxn) {
-      for (int k = tid; k < fs[f].n; k += WGS) {
-        int e;
-        if (keep) {
-          e = esum[eb + k];
-        } else {
-          const int32_t *U, *V;
-          frame_term(fs[f], k, RS, &U, &V);
-          e = (U[1] != 0 && V[1] != 0) ? U[0] + V[0] : (int)0x80000000;
-        }
-        int off = 0;
-        if (e != (int)0x80000000) {
-          off = e - base;
-          if (off < 0 || off > S) off = 0;  // only after a spread error (already flagged)
-        }
-        offs[fd[f].obase + k] = (int8_t)off;
+    for (int j = 0; j < fs[f].nparts; ++j) {
+      FramePart &q = fs[f].p[j];
+      if (q.hU && q.hV) continue;
+      for (int k = tid; k < q.n; k += WGS) {
+        const int e = ((const l_i32 *)esum)[ob + k];
+        ((l_i8 *)offs)[ob + k] = (int8_t)(e == HZ ? 0 : min(max(e - base, 0), S));
       }
+      if (tid == 0) q.ot = offs + ob;
+      ob += (q.n + 15) & ~15;
     }
-    eb += fs[f].n;
   }
   __syncthreads();
 }
 
-// Frame setup for frames of exactly one term each (the Horner products):
-// thread 0 only, no workgroup reduction.
-__device__ void frame_setup_single(const FrameSrc *fs, FrameD *fd, int nf, int nd,
-                                   int8_t *offs, int maxn) {
+// Frame setup for frames of exactly one term each whose rows are in LDS
+// (the Horner products): thread 0 only, no workgroup reduction.
+__device__ void frame_setup_single(const FrameSrc *fs, FrameD *fd, int nf, int nd, int RS) {
   const int MT = (nd + TQ - 1) / TQ;
-  long long c = 0;
   for (int f = 0; f < nf; ++f) {
     FrameD d;
-    const int32_t *U = fs[f].p[0].U, *V = fs[f].p[0].V;
+    const l_i32 *U = (const l_i32 *)fs[f].p[0].U, *V = (const l_i32 *)fs[f].p[0].V;
+    const int e = (U[1] != 0 && V[1] != 0) ? U[0] + V[0] : HZ;
     d.n = 1;
-    d.nz = (U[1] != 0 && V[1] != 0) ? 1 : 0;
-    d.base = d.nz ? U[0] + V[0] : 0;
+    d.nz = e != HZ ? 1 : 0;
+    d.base = d.nz ? e : 0;
     d.S = 0;
     d.NT = MT;
-    d.obase = 16 * f;
-    d.cost0 = c;
-    if (d.nz) c += (long long)MT * MT;
+    d.mt0 = 0;
+    d.MTf = MT;
+    d.pad = 0;
     fd[f] = d;
-    offs[16 * f] = 0;
   }
-  fd[nf].cost0 = c;
 }
 
 // Columns spanned by frame f's tiles: [0, (MT + NT) * 8 + 8).
@@ -368,10 +380,10 @@ __device__ __forceinline__ int frame_cols(const FrameD &d, int nd) {
   return (MT + d.NT) * TQ + TQ;
 }
 
-__device__ __forceinline__ void tile_load(int32_t (&uu)[TQ], int32_t (&vv)[TQ], const int32_t *U,
-                                          const int32_t *V, int mt, int nt, int off) {
-  const int32_t *u = U + HDR + RPAD + mt * TQ;
-  const int32_t *v = V + HDR + RPAD + nt * TQ - off;
+__device__ __forceinline__ void tile_load_g(int32_t (&uu)[TQ], int32_t (&vv)[TQ], const g_i32 *U,
+                                            const g_i32 *V, int mt, int nt, int off) {
+  const g_i32 *u = U + HDR + RPAD + mt * TQ;
+  const g_i32 *v = V + HDR + RPAD + nt * TQ - off;
 #pragma unroll
   for (int r = 0; r < TQ; ++r) uu[r] = u[r];
 #pragma unroll
@@ -388,42 +400,152 @@ __device__ __forceinline__ void tile_fma(long long (&acc)[16], const int32_t (&u
 
 __device__ __forceinline__ void acc_flush(long long (&acc)[16], long long *col) {
   tile_normalize(acc);
+  l_i64 *c = (l_i64 *)col;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
-    if (acc[r] != 0) atomicAdd((unsigned long long *)(col + r), (unsigned long long)acc[r]);
+    if (acc[r] != 0) __hip_atomic_fetch_add((unsigned long long __attribute__((address_space(3))) *)(c + r),
+                                            (unsigned long long)acc[r], __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_WORKGROUP);
     acc[r] = 0;
   }
 }
 
+// Terms per batch of the product loop: the digits of one batch are loaded
+// while the previous batch's products are formed.
+constexpr int PB = 4;
+// Cost of a tile's own segment in the work partition, in terms.
+constexpr int TILE_OVH = 6;
+
+// Digits of term k of part pt for tile (mt, nt); the term's offset comes
+// from the part's table (TAB) or from its exponent caches (LDS either way).
+template <bool TAB>
+__device__ __forceinline__ void term_load(int32_t (&u)[TQ], int32_t (&v)[TQ], const FramePart &pt,
+                                          int k, int RS, int mt, int nt, int base, int S) {
+  int iu, iv;
+  part_rows(pt, k, &iu, &iv);
+  const g_i32 *U = (const g_i32 *)pt.U + iu * RS, *V = (const g_i32 *)pt.V + iv * RS;
+  int off;
+  if (TAB) {
+    off = ((const l_i8 *)pt.ot)[k];
+  } else {
+    const int eu = ((const l_i32 *)pt.hU)[iu], ev = ((const l_i32 *)pt.hV)[iv];
+    off = (eu == HZ || ev == HZ) ? 0 : min(max(eu + ev - base, 0), S);
+  }
+  tile_load_g(u, v, U, V, mt, nt, off);
+}
+
+// Terms [k0, k1) of part pt (rows in global memory) into the 16 column sums
+// of tile (mt, nt).  Two register batches of PB terms alternate: one is
+// being loaded while the other's products are formed.  Loads are issued
+// unconditionally (past the end they repeat the last term, whose products
+// are then skipped), so that each wait covers exactly the batch it needs.
+// The sums are carry-normalised after every 2 PB terms (2 PB <= FLUSH_TERMS
+// keeps them inside 64 bits).
+template <bool TAB>
+__device__ __forceinline__ void part_tile_terms_t(long long (&acc)[16], const FramePart &pt,
+                                                  int k0, int k1, int RS, int mt, int nt,
+                                                  int base, int S) {
+  int32_t ua[PB][TQ], va[PB][TQ], ub[PB][TQ], vb[PB][TQ];
+  const int kl = k1 - 1;
+#pragma unroll
+  for (int j = 0; j < PB; ++j) term_load<TAB>(ua[j], va[j], pt, min(k0 + j, kl), RS, mt, nt, base, S);
+  for (int k = k0; k < k1; k += 2 * PB) {
+#pragma unroll
+    for (int j = 0; j < PB; ++j)
+      term_load<TAB>(ub[j], vb[j], pt, min(k + PB + j, kl), RS, mt, nt, base, S);
+#pragma unroll
+    for (int j = 0; j < PB; ++j)
+      if (k + j < k1) tile_fma(acc, ua[j], va[j]);
+#pragma unroll
+    for (int j = 0; j < PB; ++j)
+      term_load<TAB>(ua[j], va[j], pt, min(k + 2 * PB + j, kl), RS, mt, nt, base, S);
+#pragma unroll
+    for (int j = 0; j < PB; ++j)
+      if (k + PB + j < k1) tile_fma(acc, ub[j], vb[j]);
+    tile_normalize(acc);
+  }
+}
+
+__device__ __forceinline__ void part_tile_terms(long long (&acc)[16], const FramePart &pt,
+                                                int k0, int k1, int RS, int mt, int nt,
+                                                int base, int S) {
+  if (pt.ot) part_tile_terms_t<true>(acc, pt, k0, k1, RS, mt, nt, base, S);
+  else if (pt.hU && pt.hV) part_tile_terms_t<false>(acc, pt, k0, k1, RS, mt, nt, base, S);
+  // else: no offsets (a flagged table overflow); the frame is already wrong
+}
+
 // The workgroup `rank` of `G` accumulates its share of all frames' tiles
-// into the LDS column arrays lf[f * WB + c].  Tiles are dealt to workgroups
-// in contiguous ranges (anti-diagonal order) of equal cost (tiles x terms).
-// Inside the workgroup the (tile, term) pairs are split evenly over the
-// threads in tile-major order, so a thread walks consecutive terms of
-// consecutive tiles; it keeps its 16 column sums in registers while it stays
-// on one anti-diagonal and adds them into LDS when it leaves it.  The next
-// term's digits are loaded before the current term's products are formed.
-// Returns through span[2f], span[2f+1] the column range this workgroup
-// touched in frame f (empty: lo >= hi).
-__device__ void frames_accumulate(const FrameSrc *fs, const FrameD *fd, int nf, int nd, int RS,
-                                  int WB, long long *lf, int rank, int G, int *span,
-                                  const int8_t *offs, int maxn) {
+// into the LDS column arrays lf[f * WB + c]; every row is in global memory.
+//
+// With G a multiple of 8 (G >= 16) the group is split into 8 term groups,
+// workgroup r in group r mod 8 (consecutive workgroups are dispatched to
+// different XCDs, so a term group is one XCD's share): term group x takes
+// the terms [n x / 8, n (x + 1) / 8) of every frame, so the rows it reads
+// stay in its own L2.  Within a term group, the tiles (all of the group's
+// terms each) are dealt to workgroups in contiguous ranges (anti-diagonal
+// order) of equal cost.  Inside the workgroup the (tile, term) pairs are
+// split evenly over the threads in tile-major order, so a thread walks
+// consecutive terms of consecutive tiles; it keeps its 16 column sums in
+// registers while it stays on one anti-diagonal and adds them into LDS
+// when it leaves it.  Returns through span[2f], span[2f+1] the column range
+// this workgroup touched in frame f (empty: lo >= hi).
+__device__ void frames_accumulate(const FrameSrc *fs_, const FrameD *fd_, int nf, int nd, int RS,
+                                  int WB, long long *lf, int rank, int G, int *span_) {
   const int tid = threadIdx.x;
-  const int MT = (nd + TQ - 1) / TQ;
-  const long long C = fd[nf].cost0;
-  const long long lo = C * rank / G, hi = C * (rank + 1) / G;
-  int t0[NFR], t1[NFR];
-  long long w = 0;
+  // the descriptors live in LDS: read them as such (no flat accesses here)
+  const l_FrameSrc *fs = (const l_FrameSrc *)fs_;
+  const l_FrameD *fd = (const l_FrameD *)fd_;
+  l_i32 *span = (l_i32 *)span_;
+  const int X = (G >= 16 && (G & 7) == 0) ? 8 : 1;
+  const int xg = rank % X, sub = rank / X, GS = G / X;
+  // (tile, term) items of this term group: fewer than 2^31 for every
+  // supported size, so the partition runs in 32-bit arithmetic
+  // Frames with fewer terms than term groups (the single products of the
+  // newest rows) are not split by terms: their tiles are dealt over all G
+  // workgroups, one tile range each, apart from the term groups' shares.
+  int ka[NFR], len[NFR], t0[NFR], t1[NFR];
+  bool small[NFR];
+  unsigned C = 0, Cs = 0;
+#pragma unroll
+  for (int f = 0; f < NFR; ++f) {
+    ka[f] = len[f] = 0;
+    small[f] = false;
+    if (f >= nf || !fd[f].nz) continue;
+    const unsigned n = (unsigned)fd[f].n;
+    if (X > 1 && n < (unsigned)X) {
+      small[f] = true;
+      len[f] = (int)n;
+      Cs += (unsigned)(fd[f].MTf * fd[f].NT);
+      continue;
+    }
+    ka[f] = (int)(n * xg / X);
+    len[f] = (int)(n * (xg + 1) / X) - ka[f];
+    if (len[f] > 0) C += (unsigned)(fd[f].MTf * fd[f].NT) * (unsigned)(len[f] + TILE_OVH);
+  }
+  const unsigned cq = C / GS, cr = C - cq * GS;
+  const unsigned lo = cq * sub + cr * sub / GS, hi = cq * (sub + 1) + cr * (sub + 1) / GS;
+  const unsigned sq = Cs / G, sr = Cs - sq * G;
+  const unsigned slo = sq * rank + sr * rank / G, shi = sq * (rank + 1) + sr * (rank + 1) / G;
+  unsigned pre = 0, spre = 0, w = 0;
 #pragma unroll
   for (int f = 0; f < NFR; ++f) {
     t0[f] = t1[f] = 0;
-    if (f >= nf || !fd[f].nz || fd[f].n == 0) continue;
-    long long pre = fd[f].cost0;
-    long long n = fd[f].n;
-    long long T = (long long)MT * fd[f].NT;
-    long long a = lo - pre, b = hi - pre;
-    long long ta = a <= 0 ? 0 : (a + n - 1) / n;
-    long long tb = b <= 0 ? 0 : (b + n - 1) / n;
+    if (f >= nf || len[f] == 0) continue;
+    const unsigned n = (unsigned)len[f];
+    const unsigned T = (unsigned)(fd[f].MTf * fd[f].NT);
+    unsigned ta, tb;
+    if (small[f]) {
+      ta = slo <= spre ? 0u : slo - spre;
+      tb = shi <= spre ? 0u : shi - spre;
+      spre += T;
+    } else {
+      // a tile of this group costs its terms plus a fixed overhead (its own
+      // segment: coordinates, first loads, flush)
+      const unsigned nc = n + TILE_OVH;
+      ta = lo <= pre ? 0u : (lo - pre + nc - 1) / nc;
+      tb = hi <= pre ? 0u : (hi - pre + nc - 1) / nc;
+      pre += T * nc;
+    }
     if (ta > T) ta = T;
     if (tb > T) tb = T;
     t0[f] = (int)ta;
@@ -436,93 +558,114 @@ __device__ void frames_accumulate(const FrameSrc *fs, const FrameD *fd, int nf, 
     const int f = tid;
     if (t1[f] > t0[f]) {
       int mt, nt;
-      tile_coords(t0[f], MT, fd[f].NT, &mt, &nt);
-      int dlo = mt + nt;
-      tile_coords(t1[f] - 1, MT, fd[f].NT, &mt, &nt);
-      int dhi = mt + nt;
+      tile_coords(t0[f], fd[f].MTf, fd[f].NT, &mt, &nt);
+      int dlo = mt + nt + fd[f].mt0;
+      tile_coords(t1[f] - 1, fd[f].MTf, fd[f].NT, &mt, &nt);
+      int dhi = mt + nt + fd[f].mt0;
       span[2 * f] = min(dlo, dhi) * TQ;
       span[2 * f + 1] = max(dlo, dhi) * TQ + 2 * TQ;
     }
   }
   if (w == 0) return;
-  long long q = w * tid / WGS;
-  const long long qend = w * (tid + 1) / WGS;
+  unsigned q = (unsigned)(((unsigned long long)w * tid) / WGS);
+  const unsigned qend = (unsigned)(((unsigned long long)w * (tid + 1)) / WGS);
   long long acc[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0;
   int cur_f = -1, cur_d = -1;
-  int since = 0;
   int f = 0;
-  long long fstart = 0;  // first item of frame f in the workgroup's list
+  unsigned fstart = 0;  // first item of frame f in the workgroup's list
   while (q < qend) {
     // frame of item q
-    while (f < nf && q >= fstart + (long long)(t1[f] - t0[f]) * fd[f].n) {
-      fstart += (long long)(t1[f] - t0[f]) * fd[f].n;
+    while (f < nf && q >= fstart + (unsigned)(t1[f] - t0[f]) * (unsigned)len[f]) {
+      fstart += (unsigned)(t1[f] - t0[f]) * (unsigned)len[f];
       ++f;
     }
-    const int n = fd[f].n;
-    const long long rel = q - fstart;
-    const int t = t0[f] + (int)(rel / n);
-    const int k0 = (int)(rel % n);
-    const long long seg_end = min(qend, fstart + (long long)(t - t0[f] + 1) * n);
-    const int k1 = k0 + (int)(seg_end - q);
+    const unsigned n = (unsigned)len[f];
+    const unsigned rel = q - fstart;
+    const unsigned tr = rel / n;
+    const int t = t0[f] + (int)tr;
+    const int kk0 = (int)(rel - tr * n);
+    const unsigned seg_end = min(qend, fstart + (tr + 1) * n);
     int mt, nt;
-    tile_coords(t, MT, fd[f].NT, &mt, &nt);
+    tile_coords(t, fd[f].MTf, fd[f].NT, &mt, &nt);
+    mt += fd[f].mt0;
     const int d = mt + nt;
     if (f != cur_f || d != cur_d) {
       if (cur_f >= 0) acc_flush(acc, lf + (size_t)cur_f * WB + cur_d * TQ);
       cur_f = f;
       cur_d = d;
-      since = 0;
     }
-    const int8_t *of = offs + fd[f].obase;
-    const int Sf = fd[f].S;
-    const FrameSrc &src = fs[f];
-    // walk the segment part by part with pointer strides (no per-term dispatch)
-    int k = k0;
+    // frame terms [k, k1), walked part by part
+    const l_FrameSrc &src = fs[f];
+    const int nparts = src.nparts, fbase = fd[f].base, fS = fd[f].S;
+    int k = ka[f] + kk0;
+    const int k1 = k + (int)(seg_end - q);
+    int j = 0, pbase = 0;
     while (k < k1) {
-      int j = 0, kl = k;
-      while (j + 1 < src.nparts && kl >= src.p[j].n) {
-        kl -= src.p[j].n;
+      while (j + 1 < nparts && k >= pbase + src.p[j].n) {
+        pbase += src.p[j].n;
         ++j;
       }
-      const FramePart &pt = src.p[j];
-      const int kend = min(k1, k - kl + pt.n);
-      const int32_t *U, *V;
-      part_term(pt, kl, RS, &U, &V);
-      const long long dU = pt.kind == PK_CAUCHY ? -(long long)RS : (pt.kind == PK_ONE ? 0 : RS);
-      const long long dV = pt.kind == PK_ONE ? 0 : RS;
-      int32_t ua[TQ], va[TQ], ub[TQ], vb[TQ];
-      tile_load(ua, va, U, V, mt, nt, min(max((int)of[k], 0), Sf));
-      while (k < kend) {
-        if (k + 1 < kend) {
-          U += dU;
-          V += dV;
-          tile_load(ub, vb, U, V, mt, nt, min(max((int)of[k + 1], 0), Sf));
-        }
-        tile_fma(acc, ua, va);
-        if (++since == FLUSH_TERMS) {
-          tile_normalize(acc);
-          since = 0;
-        }
-        ++k;
-        if (k >= kend) break;
-        if (k + 1 < kend) {
-          U += dU;
-          V += dV;
-          tile_load(ua, va, U, V, mt, nt, min(max((int)of[k + 1], 0), Sf));
-        }
-        tile_fma(acc, ub, vb);
-        if (++since == FLUSH_TERMS) {
-          tile_normalize(acc);
-          since = 0;
-        }
-        ++k;
-      }
+      FramePart pt;
+      pt.kind = src.p[j].kind;
+      pt.n = src.p[j].n;
+      pt.idx = src.p[j].idx;
+      pt.pad = 0;
+      pt.U = src.p[j].U;
+      pt.V = src.p[j].V;
+      pt.hU = src.p[j].hU;
+      pt.hV = src.p[j].hV;
+      pt.ot = src.p[j].ot;
+      const int kend = min(k1, pbase + pt.n);
+      part_tile_terms(acc, pt, k - pbase, kend - pbase, RS, mt, nt, fbase, fS);
+      k = kend;
     }
     q = seg_end;
   }
   if (cur_f >= 0) acc_flush(acc, lf + (size_t)cur_f * WB + cur_d * TQ);
+}
+
+// One-term frames f = 0..nf-1 whose two rows are in LDS (the Horner
+// products), computed by the whole workgroup into lf[f * WB + c].  The
+// tiles of each anti-diagonal (which share their 16 columns) are cut into
+// runs of up to DRUN tiles; a thread sums a run in registers and adds it
+// into LDS once, so few atomics meet on one column.
+constexpr int DRUN = 4;
+
+__device__ void lds_products(const FrameSrc *fs, const FrameD *fd, int nf, int nd, int WB,
+                             long long *lf) {
+  const int tid = threadIdx.x;
+  const int MT = (nd + TQ - 1) / TQ;
+  const int ND = 2 * MT - 1;                 // anti-diagonals
+  const int CPD = (MT + DRUN - 1) / DRUN;    // run slots per diagonal
+  const int slots = ND * CPD;
+  for (int f = 0; f < nf; ++f) {
+    if (!fd[f].nz) continue;
+    const l_i32 *U = (const l_i32 *)fs[f].p[0].U + HDR + RPAD;
+    const l_i32 *V = (const l_i32 *)fs[f].p[0].V + HDR + RPAD;
+    for (int sl = tid; sl < slots; sl += WGS) {
+      const int d = sl / CPD, c = sl - d * CPD;
+      const int mlo = d - MT + 1 > 0 ? d - MT + 1 : 0;
+      const int mhi = d < MT - 1 ? d : MT - 1;
+      const int m0 = mlo + c * DRUN;
+      if (m0 > mhi) continue;
+      const int m1 = m0 + DRUN - 1 < mhi ? m0 + DRUN - 1 : mhi;
+      long long acc[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[r] = 0;
+      for (int mt = m0; mt <= m1; ++mt) {
+        const int nt = d - mt;
+        int32_t uu[TQ], vv[TQ];
+#pragma unroll
+        for (int r = 0; r < TQ; ++r) uu[r] = U[mt * TQ + r];
+#pragma unroll
+        for (int r = 0; r < TQ; ++r) vv[r] = V[nt * TQ + r];
+        tile_fma(acc, uu, vv);
+      }
+      acc_flush(acc, lf + (size_t)f * WB + d * TQ);
+    }
+  }
 }
 
 }  // namespace mpts

@@ -40,10 +40,11 @@ __device__ __forceinline__ long long chunk_add(long long (&v)[CM], int C, long l
   // v += x at the chunk bottom (x >= 0); returns the carry out of the chunk
 #pragma unroll
   for (int j = 0; j < CM; ++j) {
-    if (j >= C) break;
-    long long t = v[j] + x;
-    v[j] = t & DMASK;
-    x = t >> DBITS;
+    if (j < C) {
+      long long t = v[j] + x;
+      v[j] = t & DMASK;
+      x = t >> DBITS;
+    }
   }
   return x;
 }
@@ -53,10 +54,11 @@ __device__ __forceinline__ long long chunk_sub(long long (&v)[CM], int C, long l
   // v -= x at the chunk bottom (x >= 0); returns the borrow out of the chunk
 #pragma unroll
   for (int j = 0; j < CM; ++j) {
-    if (j >= C) break;
-    long long t = v[j] - x;
-    v[j] = t & DMASK;
-    x = -(t >> DBITS);
+    if (j < C) {
+      long long t = v[j] - x;
+      v[j] = t & DMASK;
+      x = -(t >> DBITS);
+    }
   }
   return x;
 }
@@ -66,8 +68,9 @@ __device__ __forceinline__ bool chunk_all(const long long (&v)[CM], int C, long 
   bool all = true;
 #pragma unroll
   for (int j = 0; j < CM; ++j) {
-    if (j >= C) break;
-    all &= (v[j] == val);
+    if (j < C) {
+      all &= (v[j] == val);
+    }
   }
   return all;
 }
@@ -94,17 +97,19 @@ __device__ __forceinline__ bool wave_borrow(long long (&v)[CM], int C, bool b) {
 // sign and a magnitude of 64*C digits in [0, 2^28) written to dig[0..64*C).
 // Returns -1, 0 or +1; *ovf is set when the magnitude does not fit.
 template <int CM>
-__device__ int wave_resolve_regs(long long (&v)[CM], int C, int32_t *dig, bool *ovf) {
+__device__ __forceinline__ int wave_resolve_regs(long long (&v)[CM], int C, int32_t *dig_, bool *ovf) {
   const int lane = lane_id();
+  l_i32 *dig = (l_i32 *)dig_;
   const int lo = lane * C;
   // local carry propagation: digits in [0, 2^28) and a signed chunk carry
   long long carry = 0;
 #pragma unroll
   for (int j = 0; j < CM; ++j) {
-    if (j >= C) break;
-    long long t = v[j] + carry;
-    v[j] = t & DMASK;
-    carry = t >> DBITS;
+    if (j < C) {
+      long long t = v[j] + carry;
+      v[j] = t & DMASK;
+      carry = t >> DBITS;
+    }
   }
   long long top = __shfl(carry, 63, 64);
   long long cin = shfl_up1(carry);
@@ -121,8 +126,9 @@ __device__ int wave_resolve_regs(long long (&v)[CM], int C, int32_t *dig, bool *
     // negative: magnitude = 2^(28*64C) - v
 #pragma unroll
     for (int j = 0; j < CM; ++j) {
-      if (j >= C) break;
-      v[j] = DMASK - v[j];
+      if (j < C) {
+        v[j] = DMASK - v[j];
+      }
     }
     long long c0 = (lane == 0) ? chunk_add<CM>(v, C, 1) : 0;
     (void)wave_carry<CM>(v, C, c0 != 0);
@@ -135,18 +141,26 @@ __device__ int wave_resolve_regs(long long (&v)[CM], int C, int32_t *dig, bool *
   if (__ballot(nz) == 0ull) sign = 0;
 #pragma unroll
   for (int j = 0; j < CM; ++j) {
-    if (j >= C) break;
-    dig[lo + j] = (int32_t)v[j];
+    if (j < C) {
+      dig[lo + j] = (int32_t)v[j];
+    }
   }
   __builtin_amdgcn_wave_barrier();
   return sign;
 }
 
+// floor(b / 28) and b mod 28 for any int b.
+__device__ __forceinline__ int fdiv28(int b, int *r) {
+  const int k = b >= 0 ? b / DBITS : -((-b + DBITS - 1) / DBITS);
+  *r = b - k * DBITS;
+  return k;
+}
+
 // 32 bits of a digit vector starting at bit position b (bits outside
 // [0, 28 n) read as zero).
-__device__ __forceinline__ uint32_t dig_bits32(const int32_t *dig, int n, long long b) {
-  long long k = b >= 0 ? b / DBITS : -((-b + DBITS - 1) / DBITS);
-  int r = (int)(b - k * DBITS);  // 0..27
+__device__ __forceinline__ uint32_t dig_bits32(const l_i32 *dig, int n, int b) {
+  int r;
+  const int k = fdiv28(b, &r);  // r in 0..27
   // the 32-bit window spans at most three digits
   unsigned long long d0 = (k >= 0 && k < n) ? (uint32_t)dig[k] : 0u;
   unsigned long long d1 = (k + 1 >= 0 && k + 1 < n) ? (uint32_t)dig[k + 1] : 0u;
@@ -157,7 +171,7 @@ __device__ __forceinline__ uint32_t dig_bits32(const int32_t *dig, int n, long l
 
 // Highest nonzero digit index of dig[0..64C) (-1 if all zero); every lane
 // gets the result.
-__device__ __forceinline__ int wave_top_digit(const int32_t *dig, int C) {
+__device__ __forceinline__ int wave_top_digit(const l_i32 *dig, int C) {
   const int lane = lane_id();
   int hi = -1;
   for (int j = 0; j < C; ++j)
@@ -172,10 +186,12 @@ __device__ __forceinline__ int wave_top_digit(const int32_t *dig, int C) {
 // normalised form out = [sign, E, M[0..L)].  sticky_in marks a nonzero value
 // below the digit vector (a division remainder).  Returns false on exponent
 // overflow.
-__device__ bool wave_round(const int32_t *dig, int C, int sign, long long dexp, bool sticky_in,
-                           int L, int32_t *out) {
+__device__ bool wave_round(const int32_t *dig_, int C, int sign, long long dexp, bool sticky_in,
+                           int L, int32_t *out_) {
   const int lane = lane_id();
   const int n = 64 * C;
+  const l_i32 *dig = (const l_i32 *)dig_;
+  l_i32 *out = (l_i32 *)out_;
   int t = wave_top_digit(dig, C);
   if (t < 0 || sign == 0) {
     for (int j = lane; j < L + 2; j += 64) out[j] = 0;
@@ -183,18 +199,18 @@ __device__ bool wave_round(const int32_t *dig, int C, int sign, long long dexp, 
     return true;
   }
   uint32_t dt = (uint32_t)dig[t];
-  long long B = (long long)t * DBITS + (31 - __clz(dt));  // leading bit index
-  long long p = 32LL * L;
-  long long sh = B + 1 - p;  // bits dropped below the mantissa (may be <= 0)
+  const int B = t * DBITS + (31 - __clz(dt));  // leading bit index
+  const int p = 32 * L;
+  int sh = B + 1 - p;  // bits dropped below the mantissa (may be <= 0)
   bool rbit = false, sticky = sticky_in;
   if (sh > 0) {
-    long long rb = sh - 1;  // round bit position
-    long long kr = rb / DBITS;
-    int rr = (int)(rb - kr * DBITS);
+    const int rb = sh - 1;  // round bit position
+    const int kr = rb / DBITS;
+    const int rr = rb - kr * DBITS;
     // sticky: any bit below rb
     bool s = false;
     for (int j = 0; j < C; ++j) {
-      long long k = (long long)lane * C + j;
+      const int k = lane * C + j;
       if (k < kr) s |= (dig[k] != 0);
       if (k == kr) {
         uint32_t d = (uint32_t)dig[k];
@@ -213,7 +229,7 @@ __device__ bool wave_round(const int32_t *dig, int C, int sign, long long dexp, 
     mv[j] = 0u;
     if (j >= CL) continue;
     int li = lane * CL + j;
-    if (li < L) mv[j] = dig_bits32(dig, n, sh + 32LL * li);
+    if (li < L) mv[j] = dig_bits32(dig, n, sh + 32 * li);
   }
   bool lsb = (__shfl((int)(mv[0] & 1u), 0, 64) & 1) != 0;
   bool up = rbit && (sticky || lsb);
@@ -262,7 +278,7 @@ __device__ bool wave_round(const int32_t *dig, int C, int sign, long long dexp, 
       sh += 1;
     }
   }
-  long long E = dexp * DBITS + sh;
+  long long E = dexp * DBITS + (long long)sh;
   bool ok = (E > -(1LL << 30) && E < (1LL << 30));
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
@@ -296,11 +312,13 @@ __device__ __forceinline__ long long divmod_small(long long val, int d, double i
 // final remainder.  Short magnitudes are extended with zero digits at the
 // bottom until the quotient has p + 2 bits.  q is scratch of 64*CM digits.
 template <int CM>
-__device__ bool wave_div_round(const int32_t *dig, int C, int sign, long long dexp, int d, int L,
-                               int nd, int32_t *q, int32_t *out) {
+__device__ __forceinline__ bool wave_div_round(const int32_t *dig_, int C, int sign, long long dexp, int d, int L,
+                               int nd, int32_t *q_, int32_t *out) {
   const int lane = lane_id();
+  const l_i32 *dig = (const l_i32 *)dig_;
+  l_i32 *q = (l_i32 *)q_;
   int t = wave_top_digit(dig, C);
-  if (t < 0 || sign == 0) return wave_round(dig, C, 0, 0, false, L, out);
+  if (t < 0 || sign == 0) return wave_round(dig_, C, 0, 0, false, L, out);
   uint32_t dt = (uint32_t)dig[t];
   const int keep = nd + 3;
   int lowcut = t + 1 - keep;
@@ -312,8 +330,8 @@ __device__ bool wave_div_round(const int32_t *dig, int C, int sign, long long de
     if (k < lowcut) lz |= (dig[k] != 0);
   }
   const bool low_nz = __ballot(lz) != 0ull;
-  long long bits = (long long)(t - lowcut) * DBITS + (32 - __clz(dt));  // window bit length
-  long long need = 32LL * L + 16;
+  const int bits = (t - lowcut) * DBITS + (32 - __clz(dt));  // window bit length
+  const int need = 32 * L + 16;
   int m = 0;
   if (bits < need) m = (int)((need - bits + DBITS - 1) / DBITS);
   int n2 = t + 1 - lowcut + m;  // dividend digits: dig[lowcut..t] shifted up by m
@@ -355,7 +373,7 @@ __device__ bool wave_div_round(const int32_t *dig, int C, int sign, long long de
   }
   bool sticky = (__shfl((int)(r != 0), 0, 64) != 0) || low_nz;
   __builtin_amdgcn_wave_barrier();
-  return wave_round(q, C2, sign, dexp + lowcut - m, sticky, L, out);
+  return wave_round(q_, C2, sign, dexp + lowcut - m, sticky, L, out);
 }
 
 }  // namespace mpts
