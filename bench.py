@@ -125,16 +125,18 @@ def run_single(args):
         "wall_s": wall,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT_VALU_PEAK / 1e12,
                      "unit": "T limb-MAC/s", "frac": achieved / INT_VALU_PEAK,
-                     "traffic": traffic_from_profiles(args.workload)},
+                     "traffic": traffic_from_profiles(args.workload, args.steps)},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = oracle_baseline(args.workload)
     print(json.dumps(line), flush=True)
 
 
-def traffic_from_profiles(workload: str):
-    """HBM bytes per launch of the forward kernel from the committed counter
-    summary, when it was taken on the current kernel source (else null)."""
+def traffic_from_profiles(workload: str, steps: int):
+    """HBM bytes of one launch of `steps` steps of the forward kernel, from the
+    committed counter summary (measured on a launch of its own step count and
+    scaled by steps), when it was taken on the current kernel source (else
+    null)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"k_run_{workload}_traffic.txt")
     if not os.path.exists(path):
@@ -151,8 +153,8 @@ def traffic_from_profiles(workload: str):
     if fields.get("source_sha256") != h.hexdigest():
         return None
     try:
-        return float(fields["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
+        return float(fields["hbm_bytes_per_launch"]) * steps / int(fields["steps"])
+    except (KeyError, ValueError, ZeroDivisionError):
         return None
 
 
