@@ -20,28 +20,32 @@ constexpr int TQ = 8;                          // tile edge in digits (8x8 produ
 constexpr int WGS = 256;                       // threads per workgroup
 constexpr int SMAX = 16;                       // largest exponent spread (digits) of one exact sum
 constexpr int HDR = 8;                         // row header words
-constexpr int RPAD = 24;                       // zero digits on each side of a row
+constexpr int RPAD = 40;                       // zero digits on each side of a row
 constexpr int NFR = 5;                         // product frames per coefficient index
 constexpr int FLUSH_TERMS = 15;                // terms between accumulator carry-normalisations
 
 // constant rows (each a p-bit value converted to a row at kernel start)
 enum { C_SIGMA = 0, C_NSIGMA, C_R, C_NB, C_TAU, C_ONE, NCONST };
 
-// sync words, each on its own 128-byte line: NSPLIT arrival counters and
-// NSPLIT copies of the publication flag (workgroup r uses copy r mod NSPLIT,
-// so that no single line takes every workgroup's atomics or polls), the
-// error word and the Horner completion counter
+// sync words, each on its own 128-byte line: NSPLIT arrival counters,
+// NSPLIT copies of the publication flag and NSPLIT copies of the
+// coefficient-row flag (six 64-bit words: generation and one header word of
+// each new row), workgroup r using copy r mod NSPLIT so that no single line
+// takes every workgroup's atomics or polls; the error word and the Horner
+// completion counter
 constexpr int NSPLIT = 8;
-enum { SY_ARRIVE = 0, SY_FLAG = 32 * NSPLIT, SY_ERROR = 64 * NSPLIT, SY_HDONE = 64 * NSPLIT + 32,
-       SY_WORDS = 64 * NSPLIT + 64 };
+enum { SY_ARRIVE = 0, SY_FLAG = 32 * NSPLIT, SY_HFLAG = 64 * NSPLIT, SY_ERROR = 96 * NSPLIT,
+       SY_HDONE = 96 * NSPLIT + 32, SY_WORDS = 96 * NSPLIT + 64 };
 
 enum { MODE_INTEGRATE = 0, MODE_COEFFS = 1, MODE_ADJOINT = 2 };
 
 __host__ __device__ inline int digits_per_row(int L) { return (32 * L + DBITS - 1 + DBITS - 1) / DBITS; }
 inline int row_stride(int nd) { int rs = HDR + RPAD + nd + RPAD + TQ; return (rs + 31) & ~31; }
 // frame width in columns: products of two rows span 2 nd - 1 columns, plus the
-// spread, plus the tile overhang of the last diagonal, plus carries.
-inline int frame_width(int nd) { int w = 2 * nd + SMAX + 2 * TQ + 8; return (w + 31) & ~31; }
+// term offsets (up to 2 SMAX above the frame base: the Cauchy frames take
+// their base SMAX below one term's exponent sum), plus the tile overhang of
+// the last diagonal, plus carries.
+inline int frame_width(int nd) { int w = 2 * nd + 2 * SMAX + 2 * TQ + 8; return (w + 31) & ~31; }
 // digits one single-wave big-integer task must hold (combine + division)
 inline int task_digits(int nd) { return 3 * nd + 2 * SMAX + 48; }
 // bytes of the adjoint's per-term offset tables: its frames of one index

@@ -334,11 +334,11 @@ struct Carve {
   int32_t *tnorm;      // 3 tasks x 2 normalised values, NV each (aliases trow)
   int32_t *trow;       // 3 tasks x 2 LDS rows (RS each): a rounded sum, the result
   int32_t *hrow;       // 4 LDS rows (3 Horner accumulators, tau)
-  FrameSrc *fs;        // NFR
-  FrameD *fd;          // NFR + 1
+  FrameSrc *fs;        // NFR frames of an index, then the 2 early Cauchy frames of the next
+  FrameD *fd;          // the same
   int *red;            // 64
   unsigned long long *tmark;  // phase timer: time of the last mark
-  int *span;           // 2 NFR
+  int *span;           // 2 NFR column ranges of this workgroup, then 4 of the early frames
   int *hc;             // exponent caches: [3][N+1] coefficient rows, NCONST constants, then
                        // the constants' nonzero digit ranges (2 NCONST)
   int8_t *offs;        // adjoint: per-term offset tables of parts without caches
@@ -361,15 +361,15 @@ __device__ Carve carve(unsigned char *smem, const Inst &I) {
   c.hrow = (int32_t *)p;
   p += (size_t)4 * I.RS * 4;
   c.fs = (FrameSrc *)p;
-  p += sizeof(FrameSrc) * NFR;
+  p += sizeof(FrameSrc) * (NFR + 2);
   c.fd = (FrameD *)p;
-  p += sizeof(FrameD) * (NFR + 1);
+  p += sizeof(FrameD) * (NFR + 2);
   c.red = (int *)p;
   p += 64 * 4;
   c.tmark = (unsigned long long *)p;
   p += 8;
   c.span = (int *)p;
-  p += 2 * NFR * 4;
+  p += 4 * NFR * 4;
   c.hc = (int *)p;
   p += ((size_t)3 * (I.N + 1) + 3 * NCONST) * 4;
   c.maxn = I.mode == MODE_ADJOINT ? adj_table_bytes(I.N) : 0;
@@ -395,8 +395,8 @@ __device__ __forceinline__ void prof_mark(const Inst &I, const Carve &cv, int ph
 size_t lds_bytes(int L, int N, int RS, int WB, int CM, bool adjoint) {
   const int NV = (L + 2 + 3) & ~3;
   size_t b = (size_t)NFR * WB * 8 + (size_t)3 * 64 * CM * 8 + (size_t)6 * (NV > RS ? NV : RS) * 4 +
-             (size_t)4 * RS * 4 + sizeof(FrameSrc) * NFR + sizeof(FrameD) * (NFR + 1) + 64 * 4 + 8 +
-             2 * NFR * 4 + ((size_t)3 * (N + 1) + 3 * NCONST) * 4 +
+             (size_t)4 * RS * 4 + sizeof(FrameSrc) * (NFR + 2) + sizeof(FrameD) * (NFR + 2) + 64 * 4 +
+             8 + 4 * NFR * 4 + ((size_t)3 * (N + 1) + 3 * NCONST) * 4 +
              (adjoint ? (size_t)adj_table_bytes(N) : 0);
   return (b + 255) & ~(size_t)255;
 }
@@ -555,7 +555,7 @@ __device__ void group_publish(const Inst &I, bool leader, GroupSync &gs, uint32_
 // its columns into the group's global frames.  The leader then waits for
 // every workgroup's adds.  Returns the frames the leader finalises from.
 __device__ const long long *group_bulk(const Inst &I, const Carve &cv, int nf, int rank,
-                                       GroupSync &gs, uint32_t *err) {
+                                       GroupSync &gs, uint32_t *err, bool merge_early = false) {
   const int tid = threadIdx.x;
   const int G = I.G, WB = I.WB;
   frame_setup(cv.fs, cv.fd, nf, I.nd, I.RS, cv.red, cv.offs, cv.maxn, (int *)cv.tcols,
@@ -563,6 +563,21 @@ __device__ const long long *group_bulk(const Inst &I, const Carve &cv, int nf, i
   prof_mark(I, cv, PH_SETUP);
   frames_accumulate(cv.fs, cv.fd, nf, I.nd, I.RS, WB, cv.lf, rank, G, cv.span);
   __syncthreads();
+  if (merge_early && tid < 2) {
+    // frames 0 and 1 also hold this workgroup's early products
+    int *sp = cv.span + 2 * tid;
+    const int *es = cv.span + 2 * NFR + 2 * tid;
+    if (es[0] < es[1]) {
+      if (sp[0] < sp[1]) {
+        sp[0] = min(sp[0], es[0]);
+        sp[1] = max(sp[1], es[1]);
+      } else {
+        sp[0] = es[0];
+        sp[1] = es[1];
+      }
+    }
+  }
+  if (merge_early) __syncthreads();
   prof_mark(I, cv, PH_ACCUM);
   ++gs.nbulk;
   long long *gf = I.gframes + (size_t)(gs.nbulk & 1) * NFR * WB;
@@ -594,23 +609,6 @@ __device__ const long long *group_bulk(const Inst &I, const Carve &cv, int nf, i
 
 // Leader: clear the frames it finalised from, then publish its new rows.
 // Followers: wait for the publication.
-__device__ void group_release(const Inst &I, const Carve &cv, int nf, bool leader,
-                              const long long *frames, GroupSync &gs, uint32_t *err) {
-  const int tid = threadIdx.x;
-  if (leader) {
-    __syncthreads();
-    for (int f = 0; f < nf; ++f) {
-      int nc = cv.fd[f].nz ? frame_cols(cv.fd[f], I.nd) : 0;
-      long long *fr = const_cast<long long *>(frames) + (size_t)f * I.WB;
-      for (int c = tid; c < nc; c += WGS) {
-        if (I.G > 1) st_relaxed(fr + c, 0LL);
-        else fr[c] = 0;
-      }
-    }
-  }
-  group_publish(I, leader, gs, err);
-}
-
 // Exponent cache entries: coefficient row (arr, idx) and constant row c.
 __device__ __forceinline__ int *hc_row(const Inst &I, const Carve &cv, int arr) {
   return cv.hc + (size_t)arr * (I.N + 1);
@@ -620,6 +618,99 @@ __device__ __forceinline__ int *hc_const(const Inst &I, const Carve &cv, int c) 
 }
 __device__ __forceinline__ int *hc_span(const Inst &I, const Carve &cv, int c) {
   return cv.hc + (size_t)3 * (I.N + 1) + NCONST + 2 * c;
+}
+
+// Leader: clear the frames it finalised from.  The clears are issued after
+// the publication and not waited for here: the frames (of this index parity)
+// are next written at index + 2, after the leader's next publication, whose
+// wait covers these stores.
+__device__ void clear_frames(const Inst &I, const Carve &cv, int nf, const long long *frames) {
+  const int tid = threadIdx.x;
+  for (int f = 0; f < nf; ++f) {
+    int nc = cv.fd[f].nz ? frame_cols(cv.fd[f], I.nd) : 0;
+    long long *fr = const_cast<long long *>(frames) + (size_t)f * I.WB;
+    for (int c = tid; c < nc; c += WGS) {
+      if (I.G > 1) st_relaxed(fr + c, 0LL);
+      else fr[c] = 0;
+    }
+  }
+}
+
+// Leader: publish its new rows, then clear the frames.  Followers: wait for
+// the publication.
+__device__ void group_release(const Inst &I, const Carve &cv, int nf, bool leader,
+                              const long long *frames, GroupSync &gs, uint32_t *err) {
+  group_publish(I, leader, gs, err);
+  if (leader) clear_frames(I, cv, nf, frames);
+}
+
+// Thread 0 of a follower: wait for the coefficient-row flag of generation
+// gen on its line (six 64-bit words, gen in the high half, a header word in
+// the low half: written whole, so a word that carries gen carries its value)
+// and return the six header words.
+__device__ void spin_hdr(const uint32_t *line, uint32_t gen, int *vals, uint32_t *err) {
+  const __amdgpu_buffer_rsrc_t rs = dev_rsrc(line, 48);
+  long long polls = 0;
+  while (true) {
+    unsigned long long w[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) w[j] = (unsigned long long)ld_dev64(rs, 8 * j);
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) ok &= (uint32_t)(w[j] >> 32) == gen;
+    if (ok) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) vals[j] = (int)(uint32_t)w[j];
+      return;
+    }
+    __builtin_amdgcn_s_sleep(2);
+    if (++polls > (1LL << 25)) {
+      atomicOr(err, 4u);
+      for (int j = 0; j < 6; ++j) vals[j] = 0;
+      return;
+    }
+  }
+}
+
+// Coefficient index i done: the leader publishes rows i+1 (three LDS result
+// rows of its finalisation tasks) with their headers in the coefficient-row
+// flag, then clears the frames; every workgroup caches the exponents of
+// rows i+1.
+__device__ void release_rows(const Inst &I, const Carve &cv, bool leader,
+                             const long long *frames, GroupSync &gs, int i, uint32_t *err) {
+  const int tid = threadIdx.x;
+  const int RS = I.RS;
+  // result rows of the tasks: beta (task 0) -> array 1, gamma (1) -> 2, alpha (2) -> 0
+  if (leader) {
+    wait_vmem();
+    __syncthreads();
+    ++gs.gen;
+    if (I.G > 1 && tid < 6 * NSPLIT) {
+      const int line = tid / 6, j = tid - 6 * line;
+      const int arr = j >> 1;
+      const int task = arr == 0 ? 2 : arr - 1;
+      const int v = ((const l_i32 *)(cv.trow + (size_t)(2 * task + 1) * RS))[j & 1];
+      __hip_atomic_store((unsigned long long *)(I.sync + SY_HFLAG + 32 * line) + j,
+                         ((unsigned long long)gs.gen << 32) | (uint32_t)v, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (tid < 3) {
+      const int task = tid == 0 ? 2 : tid - 1;
+      const l_i32 *row = (const l_i32 *)(cv.trow + (size_t)(2 * task + 1) * RS);
+      hc_row(I, cv, tid)[i + 1] = row[1] != 0 ? row[0] : HZ;
+    }
+    clear_frames(I, cv, NFR, frames);
+    __syncthreads();
+  } else {
+    ++gs.gen;
+    if (tid == 0) {
+      const int rank = blockIdx.x - I.wg0;
+      int v[6];
+      spin_hdr(I.sync + SY_HFLAG + 32 * (rank % NSPLIT), gs.gen, v, err);
+      for (int a = 0; a < 3; ++a) hc_row(I, cv, a)[i + 1] = v[2 * a + 1] != 0 ? v[2 * a] : HZ;
+    }
+    __syncthreads();
+  }
 }
 
 // Digit range [lo, hi] of the row of each constant that holds all its
@@ -670,13 +761,44 @@ __device__ void start_step(const Inst &I, const Carve &cv, bool leader, const in
   __syncthreads();
 }
 
+// Exponent sum of the first nonzero term U[idx - k] V[k], k = k0..k1, from
+// the exponent caches (HZ if every term is zero).
+__device__ __forceinline__ int first_esum(const int *hU, const int *hV, int idx, int k0, int k1) {
+  const l_i32 *u = (const l_i32 *)hU, *v = (const l_i32 *)hV;
+  for (int k = k0; k <= k1; ++k) {
+    const int a = u[idx - k], b = v[k];
+    if (a != HZ && b != HZ) return a + b;
+  }
+  return HZ;
+}
+
+// Base of the Cauchy frame sum_k U[i-k] V[k] of index i: SMAX digits below
+// the exponent sum of its first nonzero term, the terms k = 1..i-1 (which do
+// not involve the newest rows) taken first.  The terms of an exact sum
+// spread over at most SMAX digits, so every offset lies in [0, 2 SMAX].
+__device__ __forceinline__ int cauchy_base(const int *hU, const int *hV, int i) {
+  int e = i >= 2 ? first_esum(hU, hV, i, 1, i - 1) : HZ;
+  if (e == HZ) e = first_esum(hU, hV, i, 0, 0);
+  if (e == HZ && i > 0) e = first_esum(hU, hV, i, i, i);
+  return e == HZ ? HZ : e - SMAX;
+}
+
 // The Taylor coefficients 1..N of one step (equation (3)), rows 0 given.
+//
+// With two or more workgroups the Cauchy sums are computed one index ahead:
+// while the leader finalises index i, every other workgroup accumulates the
+// terms of the Cauchy sums of index i+1 that involve no row i+1 (k = 1..i)
+// into its LDS frames.  Once rows i+1 are published, the products with them
+// (k = 0 and k = i+1, and the three single-product frames) are dealt over the
+// whole group, and the frames go to the leader as before.  Both parts use
+// the frame base of cauchy_base, which needs no row i+1.
 template <int CM>
 __device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, GroupSync &gs,
                                      const int32_t *state, uint32_t *err) {
   const int tid = threadIdx.x, wave = tid >> 6;
   const bool leader = rank == 0;
-  const int RS = I.RS;
+  const int RS = I.RS, nd = I.nd;
+  const bool look = I.G >= 2;
   // the beta task keeps b_i in LDS (its result row): start with the row b_0
   if (leader && wave == 0) {
     const g_i32 *b0 = (const g_i32 *)row_ptr(I, 1, 0);
@@ -684,13 +806,31 @@ __device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, G
     for (int w = threadIdx.x & 63; w < RS; w += 64) dst[w] = b0[w];
   }
   (void)state;
+  const int *ha = hc_row(I, cv, 0), *hb = hc_row(I, cv, 1), *hg = hc_row(I, cv, 2);
+  auto cst = [&](int c) { return I.consts + (size_t)c * RS; };
+  int eb0 = HZ, eb1 = HZ;  // thread 0: bases of the two Cauchy frames of index i
   for (int i = 0; i < I.N; ++i) {
     if (tid == 0) {
       FrameSrc *fs = cv.fs;
-      const int *ha = hc_row(I, cv, 0), *hb = hc_row(I, cv, 1), *hg = hc_row(I, cv, 2);
-      auto cst = [&](int c) { return I.consts + (size_t)c * RS; };
-      fs[0] = mk_frame1(mk_part(PK_CAUCHY, i + 1, i, row_ptr(I, 0, 0), row_ptr(I, 2, 0), ha, hg));
-      fs[1] = mk_frame1(mk_part(PK_CAUCHY, i + 1, i, row_ptr(I, 0, 0), row_ptr(I, 1, 0), ha, hb));
+      eb0 = cauchy_base(ha, hg, i);
+      eb1 = cauchy_base(ha, hb, i);
+      if (look) {
+        // the terms with the newest rows (rows i); the others were taken early
+        if (i == 0) {
+          fs[0] = mk_frame1(mk_part(PK_ONE, 1, 0, row_ptr(I, 0, 0), row_ptr(I, 2, 0), ha, hg));
+          fs[1] = mk_frame1(mk_part(PK_ONE, 1, 0, row_ptr(I, 0, 0), row_ptr(I, 1, 0), ha, hb));
+        } else {
+          fs[0] = mk_frame2(mk_part(PK_ONE, 1, 0, row_ptr(I, 0, i), row_ptr(I, 2, 0), ha + i, hg),
+                            mk_part(PK_ONE, 1, 0, row_ptr(I, 0, 0), row_ptr(I, 2, i), ha, hg + i));
+          fs[1] = mk_frame2(mk_part(PK_ONE, 1, 0, row_ptr(I, 0, i), row_ptr(I, 1, 0), ha + i, hb),
+                            mk_part(PK_ONE, 1, 0, row_ptr(I, 0, 0), row_ptr(I, 1, i), ha, hb + i));
+        }
+      } else {
+        fs[0] = mk_frame1(mk_part(PK_CAUCHY, i + 1, i, row_ptr(I, 0, 0), row_ptr(I, 2, 0), ha, hg));
+        fs[1] = mk_frame1(mk_part(PK_CAUCHY, i + 1, i, row_ptr(I, 0, 0), row_ptr(I, 1, 0), ha, hb));
+      }
+      fs[0].fbase = eb0;
+      fs[1].fbase = eb1;
       fs[2] = mk_frame2(mk_part(PK_ONE, 1, 0, cst(C_SIGMA), row_ptr(I, 1, i),
                                 hc_const(I, cv, C_SIGMA), hb + i),
                         mk_part(PK_ONE, 1, 0, cst(C_NSIGMA), row_ptr(I, 0, i),
@@ -706,16 +846,50 @@ __device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, G
                                 hg + i));
     }
     __syncthreads();
-    const long long *frames = group_bulk(I, cv, NFR, rank, gs, err);
-    if (leader && wave < 3) finalize_task<CM>(I, cv, wave, i, frames, I.G > 1, err);
+    const long long *frames = group_bulk(I, cv, NFR, rank, gs, err, look && !leader && i >= 2);
     if (leader) {
+      // frames 0 and 1 as finalised: from their base, wide enough for every
+      // offset in [0, 2 SMAX]
+      if (tid == 0) {
+        const int eb[2] = {eb0, eb1};
+        for (int f = 0; f < 2; ++f) {
+          if (eb[f] == HZ) continue;
+          FrameD d = cv.fd[f];
+          d.nz = 1;
+          d.base = eb[f];
+          d.nt0 = 0;
+          d.S = 2 * SMAX;
+          d.NT = (nd + 2 * SMAX + TQ - 1) / TQ;
+          cv.fd[f] = d;
+        }
+      }
+      __syncthreads();
+      if (wave < 3) finalize_task<CM>(I, cv, wave, i, frames, I.G > 1, err);
+      __syncthreads();
+      prof_mark(I, cv, PH_FINAL);
+    } else if (look && i + 1 < I.N && i + 1 >= 2) {
+      // early part of index j = i+1: Cauchy terms k = 1..j-1 (rows <= i)
+      const int j = i + 1;
+      if (tid == 0) {
+        FrameSrc *fs = cv.fs + NFR;
+        const int e0 = first_esum(ha, hg, j, 1, j - 1), e1 = first_esum(ha, hb, j, 1, j - 1);
+        fs[0] = mk_frame1(mk_part(PK_CAUCHY, j - 1, j - 1, row_ptr(I, 0, 0), row_ptr(I, 2, 1), ha,
+                                  hg + 1));
+        fs[1] = mk_frame1(mk_part(PK_CAUCHY, j - 1, j - 1, row_ptr(I, 0, 0), row_ptr(I, 1, 1), ha,
+                                  hb + 1));
+        fs[0].fbase = e0 == HZ ? HZ : e0 - SMAX;
+        fs[1].fbase = e1 == HZ ? HZ : e1 - SMAX;
+      }
+      __syncthreads();
+      frame_setup(cv.fs + NFR, cv.fd + NFR, 2, nd, RS, cv.red, cv.offs, cv.maxn, (int *)cv.tcols,
+                  3 * 64 * I.CM * 2, err);
+      frames_accumulate(cv.fs + NFR, cv.fd + NFR, 2, nd, RS, I.WB, cv.lf, rank, I.G,
+                        cv.span + 2 * NFR, true);
       __syncthreads();
       prof_mark(I, cv, PH_FINAL);
     }
-    group_release(I, cv, NFR, leader, frames, gs, err);
+    release_rows(I, cv, leader, frames, gs, i, err);
     prof_mark(I, cv, PH_CLEAR);
-    // the new rows are published: cache their exponents
-    if (tid < 3) hc_row(I, cv, tid)[i + 1] = row_exp(row_ptr(I, tid, i + 1));
   }
 }
 
@@ -785,6 +959,7 @@ __global__ void __launch_bounds__(WGS) k_run(const Inst *__restrict__ insts,
   Carve cv = carve(smem, I);
   for (int j = tid; j < NFR * WB; j += WGS) cv.lf[j] = 0;
   GroupSync gs{0u, 0ull};
+  red_reset(cv.red);
   const_spans(I, cv);
   if (tid == 0) {
     *cv.tmark = wall_clock64();
@@ -897,6 +1072,7 @@ __global__ void __launch_bounds__(WGS) k_adj(const Inst *__restrict__ insts,
   for (int j = tid; j < NFR * WB; j += WGS) cv.lf[j] = 0;
   GroupSync gs{0u, 0ull};
   const bool rel = G > 1;
+  red_reset(cv.red);
   const_spans(I, cv);
   if (tid == 0) *cv.tmark = wall_clock64();
   if (leader) {

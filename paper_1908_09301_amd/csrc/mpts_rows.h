@@ -129,11 +129,16 @@ struct FramePart {
 struct FrameSrc {
   int nparts, n;  // n = total terms
   int mlo, mhi;   // digit range holding every nonzero digit of the parts' U rows
+  int fbase;      // the frame's exponent base when given (else HZ: the terms' minimum)
+  int pad;
   FramePart p[4];
 };
 
+// A frame's column c holds the digit weight 2^(28 (base + c)); term t sits at
+// offset off_t = e(U_t) + e(V_t) - base in [0, S].  Tile rows mt0 .. mt0 +
+// MTf - 1 and tile columns nt0 .. nt0 + NT - 1 can be nonzero.
 struct FrameD {
-  int n, base, S, NT, nz, mt0, MTf, pad;  // tile rows mt0 .. mt0 + MTf - 1 can be nonzero
+  int n, base, S, NT, nz, mt0, MTf, nt0;
 };
 
 typedef __attribute__((address_space(3))) FrameSrc l_FrameSrc;
@@ -194,6 +199,8 @@ __host__ __device__ inline FrameSrc mk_frame1(FramePart a) {
   f.n = a.n;
   f.mlo = 0;
   f.mhi = 0x7fffffff;
+  f.fbase = (int)0x80000000;
+  f.pad = 0;
   f.p[0] = a;
   f.p[1] = a;
   f.p[2] = a;
@@ -264,6 +271,13 @@ __device__ __forceinline__ void tile_normalize(long long (&acc)[16]) {
   }
 }
 
+// The min / max slots of frame_setup's reduction, back to their neutral
+// values (the next use is behind at least one workgroup barrier).
+__device__ __forceinline__ void red_reset(int *red) {
+  const int t = threadIdx.x;
+  if (t < 2 * NFR) ((l_i32 *)red)[t] = (t & 1) ? -0x7fffffff : 0x7fffffff;
+}
+
 // Per-workgroup frame setup: exponent base and spread of each frame's
 // nonzero terms (one workgroup reduction for all frames).  Exponents come
 // from the parts' caches (LDS) or, for parts without both caches, from the
@@ -297,45 +311,50 @@ __device__ void frame_setup(FrameSrc *fs, FrameD *fd, int nf, int nd, int RS, in
         if (!cached) ob += (q.n + 15) & ~15;
       }
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      mn[f] = min(mn[f], __shfl_xor(mn[f], o, 64));
-      mx[f] = max(mx[f], __shfl_xor(mx[f], o, 64));
-    }
-    if ((tid & 63) == 0) {
-      red[(tid >> 6) * 2 * NFR + 2 * f] = mn[f];
-      red[(tid >> 6) * 2 * NFR + 2 * f + 1] = mx[f];
+    // workgroup min / max by LDS atomics on red (reset after every use)
+    if (mn[f] <= mx[f]) {
+      __hip_atomic_fetch_min((l_i32 *)red + 2 * f, mn[f], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_fetch_max((l_i32 *)red + 2 * f + 1, mx[f], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
     }
   }
   __syncthreads();
   if (tid < nf) {
     const int f = tid;
-    int a = red[2 * f], b = red[2 * f + 1];
-    for (int w = 1; w < WGS / 64; ++w) {
-      a = min(a, red[w * 2 * NFR + 2 * f]);
-      b = max(b, red[w * 2 * NFR + 2 * f + 1]);
-    }
+    const int a = ((const l_i32 *)red)[2 * f], b = ((const l_i32 *)red)[2 * f + 1];
     FrameD d;
     d.n = fs[f].n;
     d.nz = (a <= b) ? 1 : 0;
-    d.base = d.nz ? a : 0;
-    int S = d.nz ? (b - a) : 0;
-    if (S > SMAX) {
-      atomicOr(err, 1u | 16u);
-      S = SMAX;
+    const int fb = fs[f].fbase;
+    // a given base must lie at most 2 SMAX below every term; the spread of
+    // the terms is at most SMAX either way
+    int lo = 0, S = 0;
+    if (d.nz) {
+      d.base = fb != HZ ? fb : a;
+      lo = a - d.base;
+      S = b - d.base;
+      if (b - a > SMAX || lo < 0 || S > 2 * SMAX) {
+        atomicOr(err, 1u | 16u);
+        lo = max(min(lo, 2 * SMAX), 0);
+        S = max(min(S, 2 * SMAX), lo);
+      }
+    } else {
+      d.base = fb != HZ ? fb : 0;
     }
     d.S = S;
-    d.NT = (nd + S + TQ - 1) / TQ;
+    d.nt0 = lo / TQ;
+    d.NT = (nd + S + TQ - 1) / TQ - d.nt0;
     const int MT = (nd + TQ - 1) / TQ;
     const int m0 = max(fs[f].mlo, 0) / TQ;
     const int m1 = min(fs[f].mhi, nd - 1) / TQ;
     d.mt0 = m0 < MT ? m0 : 0;
     d.MTf = m1 >= m0 && m0 < MT ? min(m1, MT - 1) - m0 + 1 : MT;
-    d.pad = 0;
     fd[f] = d;
   }
   if (tid == 0 && !fits) atomicOr(err, 8u);  // table too small: never expected
   __syncthreads();
+  red_reset(red);
   if (ob == 0 || !fits) return;
   ob = 0;
   for (int f = 0; f < nf; ++f) {
@@ -369,7 +388,7 @@ __device__ void frame_setup_single(const FrameSrc *fs, FrameD *fd, int nf, int n
     d.NT = MT;
     d.mt0 = 0;
     d.MTf = MT;
-    d.pad = 0;
+    d.nt0 = 0;
     fd[f] = d;
   }
 }
@@ -377,7 +396,7 @@ __device__ void frame_setup_single(const FrameSrc *fs, FrameD *fd, int nf, int n
 // Columns spanned by frame f's tiles: [0, (MT + NT) * 8 + 8).
 __device__ __forceinline__ int frame_cols(const FrameD &d, int nd) {
   int MT = (nd + TQ - 1) / TQ;
-  return (MT + d.NT) * TQ + TQ;
+  return (MT + d.nt0 + d.NT) * TQ + TQ;
 }
 
 __device__ __forceinline__ void tile_load_g(int32_t (&uu)[TQ], int32_t (&vv)[TQ], const g_i32 *U,
@@ -490,14 +509,29 @@ __device__ __forceinline__ void part_tile_terms(long long (&acc)[16], const Fram
 // when it leaves it.  Returns through span[2f], span[2f+1] the column range
 // this workgroup touched in frame f (empty: lo >= hi).
 __device__ void frames_accumulate(const FrameSrc *fs_, const FrameD *fd_, int nf, int nd, int RS,
-                                  int WB, long long *lf, int rank, int G, int *span_) {
+                                  int WB, long long *lf, int rank, int G, int *span_,
+                                  bool skip0 = false) {
   const int tid = threadIdx.x;
   // the descriptors live in LDS: read them as such (no flat accesses here)
   const l_FrameSrc *fs = (const l_FrameSrc *)fs_;
   const l_FrameD *fd = (const l_FrameD *)fd_;
   l_i32 *span = (l_i32 *)span_;
   const int X = (G >= 16 && (G & 7) == 0) ? 8 : 1;
-  const int xg = rank % X, sub = rank / X, GS = G / X;
+  const int xg = rank % X;
+  int sub = rank / X, GS = G / X;
+  // skip0: workgroup 0 takes no share (the others split the work)
+  int srank = rank, sG = G;
+  if (skip0) {
+    if (X == 1) {
+      sub = rank - 1;
+      GS = G - 1;
+    } else if (xg == 0) {
+      sub -= 1;
+      GS -= 1;
+    }
+    srank = rank - 1;
+    sG = G - 1;
+  }
   // (tile, term) items of this term group: fewer than 2^31 for every
   // supported size, so the partition runs in 32-bit arithmetic
   // Frames with fewer terms than term groups (the single products of the
@@ -524,8 +558,8 @@ __device__ void frames_accumulate(const FrameSrc *fs_, const FrameD *fd_, int nf
   }
   const unsigned cq = C / GS, cr = C - cq * GS;
   const unsigned lo = cq * sub + cr * sub / GS, hi = cq * (sub + 1) + cr * (sub + 1) / GS;
-  const unsigned sq = Cs / G, sr = Cs - sq * G;
-  const unsigned slo = sq * rank + sr * rank / G, shi = sq * (rank + 1) + sr * (rank + 1) / G;
+  const unsigned sq = Cs / sG, sr = Cs - sq * sG;
+  const unsigned slo = sq * srank + sr * srank / sG, shi = sq * (srank + 1) + sr * (srank + 1) / sG;
   unsigned pre = 0, spre = 0, w = 0;
 #pragma unroll
   for (int f = 0; f < NFR; ++f) {
@@ -554,14 +588,15 @@ __device__ void frames_accumulate(const FrameSrc *fs_, const FrameD *fd_, int nf
   }
   if (tid < 2 * nf) span[tid] = 0;
   __syncthreads();
+  if (skip0 && rank == 0) return;
   if (tid < nf) {
     const int f = tid;
     if (t1[f] > t0[f]) {
       int mt, nt;
       tile_coords(t0[f], fd[f].MTf, fd[f].NT, &mt, &nt);
-      int dlo = mt + nt + fd[f].mt0;
+      int dlo = mt + nt + fd[f].mt0 + fd[f].nt0;
       tile_coords(t1[f] - 1, fd[f].MTf, fd[f].NT, &mt, &nt);
-      int dhi = mt + nt + fd[f].mt0;
+      int dhi = mt + nt + fd[f].mt0 + fd[f].nt0;
       span[2 * f] = min(dlo, dhi) * TQ;
       span[2 * f + 1] = max(dlo, dhi) * TQ + 2 * TQ;
     }
@@ -590,6 +625,7 @@ __device__ void frames_accumulate(const FrameSrc *fs_, const FrameD *fd_, int nf
     int mt, nt;
     tile_coords(t, fd[f].MTf, fd[f].NT, &mt, &nt);
     mt += fd[f].mt0;
+    nt += fd[f].nt0;
     const int d = mt + nt;
     if (f != cur_f || d != cur_d) {
       if (cur_f >= 0) acc_flush(acc, lf + (size_t)cur_f * WB + cur_d * TQ);
