@@ -21,8 +21,8 @@ namespace mpts {
 template <int C>
 using chunk_t = std::integral_constant<int, C>;
 
-// Calls f(chunk_t<Ct>) with Ct the smallest power of two >= max(c, 2) that
-// is at most CMAX (c <= CMAX is the caller's contract).
+// Calls f(chunk_t<Ct>) with Ct the smallest of 2, 4, 8, 12, 16, 24, 32 that
+// is >= c and at most CMAX (c <= CMAX is the caller's contract).
 template <int CMAX, typename F>
 __device__ __forceinline__ void with_chunks(int c, F &&f) {
   if (c <= 2) {
@@ -42,12 +42,22 @@ __device__ __forceinline__ void with_chunks(int c, F &&f) {
     }
   }
   if constexpr (CMAX >= 16) {
+    if (c <= 12) {
+      f(chunk_t<12>());
+      return;
+    }
     if (c <= 16) {
       f(chunk_t<16>());
       return;
     }
   }
-  if constexpr (CMAX >= 32) f(chunk_t<32>());
+  if constexpr (CMAX >= 32) {
+    if (c <= 24) {
+      f(chunk_t<24>());
+      return;
+    }
+    f(chunk_t<32>());
+  }
 }
 
 // + x (0 <= x < 2^62) at the bottom of the lane's chunk; returns the carry out.

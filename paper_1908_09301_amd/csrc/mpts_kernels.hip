@@ -555,11 +555,18 @@ __device__ void group_publish(const Inst &I, bool leader, GroupSync &gs, uint32_
 // its columns into the group's global frames.  The leader then waits for
 // every workgroup's adds.  Returns the frames the leader finalises from.
 __device__ const long long *group_bulk(const Inst &I, const Carve &cv, int nf, int rank,
-                                       GroupSync &gs, uint32_t *err, bool merge_early = false) {
+                                       GroupSync &gs, uint32_t *err, bool merge_early = false,
+                                       bool few = false) {
   const int tid = threadIdx.x;
   const int G = I.G, WB = I.WB;
-  frame_setup(cv.fs, cv.fd, nf, I.nd, I.RS, cv.red, cv.offs, cv.maxn, (int *)cv.tcols,
-              3 * 64 * I.CM * 2, err);
+  if (few) {
+    // every frame has a few cached terms: one thread per frame
+    frame_setup_few(cv.fs, cv.fd, nf, I.nd, I.RS, err);
+    __syncthreads();
+  } else {
+    frame_setup(cv.fs, cv.fd, nf, I.nd, I.RS, cv.red, cv.offs, cv.maxn, (int *)cv.tcols,
+                3 * 64 * I.CM * 2, err);
+  }
   prof_mark(I, cv, PH_SETUP);
   frames_accumulate(cv.fs, cv.fd, nf, I.nd, I.RS, WB, cv.lf, rank, G, cv.span);
   __syncthreads();
@@ -811,7 +818,7 @@ __device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, G
   int eb0 = HZ, eb1 = HZ;  // thread 0: bases of the two Cauchy frames of index i
   for (int i = 0; i < I.N; ++i) {
     if (tid == 0) {
-      FrameSrc *fs = cv.fs;
+      FrameSrc fs[NFR];  // built in registers, stored to LDS below
       eb0 = cauchy_base(ha, hg, i);
       eb1 = cauchy_base(ha, hb, i);
       if (look) {
@@ -844,9 +851,13 @@ __device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, G
       fs[3].mhi = hc_span(I, cv, C_R)[1];
       fs[4] = mk_frame1(mk_part(PK_ONE, 1, 0, cst(C_NB), row_ptr(I, 2, i), hc_const(I, cv, C_NB),
                                 hg + i));
+#pragma unroll
+      for (int f = 0; f < NFR; ++f) lds_put(cv.fs + f, fs[f]);
     }
     __syncthreads();
-    const long long *frames = group_bulk(I, cv, NFR, rank, gs, err, look && !leader && i >= 2);
+    prof_mark(I, cv, PH_BUILD);
+    const long long *frames =
+        group_bulk(I, cv, NFR, rank, gs, err, look && !leader && i >= 2, look);
     if (leader) {
       // frames 0 and 1 as finalised: from their base, wide enough for every
       // offset in [0, 2 SMAX]
@@ -871,7 +882,7 @@ __device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, G
       // early part of index j = i+1: Cauchy terms k = 1..j-1 (rows <= i)
       const int j = i + 1;
       if (tid == 0) {
-        FrameSrc *fs = cv.fs + NFR;
+        FrameSrc fs[2];
         const int e0 = first_esum(ha, hg, j, 1, j - 1), e1 = first_esum(ha, hb, j, 1, j - 1);
         fs[0] = mk_frame1(mk_part(PK_CAUCHY, j - 1, j - 1, row_ptr(I, 0, 0), row_ptr(I, 2, 1), ha,
                                   hg + 1));
@@ -879,6 +890,8 @@ __device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, G
                                   hb + 1));
         fs[0].fbase = e0 == HZ ? HZ : e0 - SMAX;
         fs[1].fbase = e1 == HZ ? HZ : e1 - SMAX;
+        lds_put(cv.fs + NFR, fs[0]);
+        lds_put(cv.fs + NFR + 1, fs[1]);
       }
       __syncthreads();
       frame_setup(cv.fs + NFR, cv.fd + NFR, 2, nd, RS, cv.red, cv.offs, cv.maxn, (int *)cv.tcols,

@@ -144,6 +144,31 @@ struct FrameD {
 typedef __attribute__((address_space(3))) FrameSrc l_FrameSrc;
 typedef __attribute__((address_space(3))) FrameD l_FrameD;
 
+// Word copies between LDS descriptors and registers (descriptors in LDS are
+// read and written through LDS addresses, not flat ones).  The words pass
+// through an int array and memcpy: the descriptors hold pointers, which an
+// int lvalue may not alias.
+template <typename T>
+__device__ __forceinline__ T lds_get(const T *p) {
+  static_assert(sizeof(T) % 4 == 0, "descriptor of whole words");
+  int w[sizeof(T) / 4];
+  const l_i32 *s = (const l_i32 *)p;
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) w[k] = s[k];
+  T v;
+  __builtin_memcpy(&v, w, sizeof(T));
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ void lds_put(T *p, const T &v) {
+  static_assert(sizeof(T) % 4 == 0, "descriptor of whole words");
+  int w[sizeof(T) / 4];
+  __builtin_memcpy(w, &v, sizeof(T));
+  l_i32 *d = (l_i32 *)p;
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) d[k] = w[k];
+}
+
 constexpr int HZ = (int)0x80000000;  // exponent cache entry of a zero row
 
 __device__ __forceinline__ int row_exp(const int32_t *row) { return row[1] != 0 ? row[0] : HZ; }
@@ -278,6 +303,61 @@ __device__ __forceinline__ void red_reset(int *red) {
   if (t < 2 * NFR) ((l_i32 *)red)[t] = (t & 1) ? -0x7fffffff : 0x7fffffff;
 }
 
+// Descriptor of a frame whose nonzero terms have exponent sums in [a, b]
+// (a > b: no nonzero term).  A given base must lie at most 2 SMAX below
+// every term; the spread of the terms is at most SMAX either way.
+__device__ __forceinline__ FrameD make_desc(const FrameSrc &src, int a, int b, int nd,
+                                           uint32_t *err) {
+  FrameD d;
+  d.n = src.n;
+  d.nz = (a <= b) ? 1 : 0;
+  const int fb = src.fbase;
+  int lo = 0, S = 0;
+  if (d.nz) {
+    d.base = fb != HZ ? fb : a;
+    lo = a - d.base;
+    S = b - d.base;
+    if (b - a > SMAX || lo < 0 || S > 2 * SMAX) {
+      atomicOr(err, 1u | 16u);
+      lo = max(min(lo, 2 * SMAX), 0);
+      S = max(min(S, 2 * SMAX), lo);
+    }
+  } else {
+    d.base = fb != HZ ? fb : 0;
+  }
+  d.S = S;
+  d.nt0 = lo / TQ;
+  d.NT = (nd + S + TQ - 1) / TQ - d.nt0;
+  const int MT = (nd + TQ - 1) / TQ;
+  const int m0 = max(src.mlo, 0) / TQ;
+  const int m1 = min(src.mhi, nd - 1) / TQ;
+  d.mt0 = m0 < MT ? m0 : 0;
+  d.MTf = m1 >= m0 && m0 < MT ? min(m1, MT - 1) - m0 + 1 : MT;
+  return d;
+}
+
+// Frame setup for frames of a few terms each, all with both exponent
+// caches (the products with the newest rows): thread f sets up frame f, no
+// workgroup reduction; the caller synchronises the workgroup afterwards.
+__device__ __forceinline__ void frame_setup_few(const FrameSrc *fs, FrameD *fd, int nf, int nd,
+                                                int RS, uint32_t *err) {
+  const int f = threadIdx.x;
+  if (f >= nf) return;
+  const int np = ((const l_i32 *)&fs[f].nparts)[0];
+  int a = 0x7fffffff, b = -0x7fffffff;
+  for (int j = 0; j < np; ++j) {
+    const FramePart q = lds_get(&fs[f].p[j]);
+    for (int k = 0; k < q.n; ++k) {
+      const int e = part_esum(q, k, RS);
+      if (e != HZ) {
+        a = min(a, e);
+        b = max(b, e);
+      }
+    }
+  }
+  lds_put(fd + f, make_desc(lds_get(fs + f), a, b, nd, err));
+}
+
 // Per-workgroup frame setup: exponent base and spread of each frame's
 // nonzero terms (one workgroup reduction for all frames).  Exponents come
 // from the parts' caches (LDS) or, for parts without both caches, from the
@@ -296,8 +376,9 @@ __device__ void frame_setup(FrameSrc *fs, FrameD *fd, int nf, int nd, int RS, in
     mn[f] = 0x7fffffff;
     mx[f] = -0x7fffffff;
     if (f < nf) {
-      for (int j = 0; j < fs[f].nparts; ++j) {
-        const FramePart &q = fs[f].p[j];
+      const int np = ((const l_i32 *)&fs[f].nparts)[0];
+      for (int j = 0; j < np; ++j) {
+        const FramePart q = lds_get(&fs[f].p[j]);
         const bool cached = q.hU && q.hV;
         if (!cached && (ob + q.n > maxn || ob + q.n > esum_cap)) fits = false;
         for (int k = tid; k < q.n; k += WGS) {
@@ -323,34 +404,7 @@ __device__ void frame_setup(FrameSrc *fs, FrameD *fd, int nf, int nd, int RS, in
   if (tid < nf) {
     const int f = tid;
     const int a = ((const l_i32 *)red)[2 * f], b = ((const l_i32 *)red)[2 * f + 1];
-    FrameD d;
-    d.n = fs[f].n;
-    d.nz = (a <= b) ? 1 : 0;
-    const int fb = fs[f].fbase;
-    // a given base must lie at most 2 SMAX below every term; the spread of
-    // the terms is at most SMAX either way
-    int lo = 0, S = 0;
-    if (d.nz) {
-      d.base = fb != HZ ? fb : a;
-      lo = a - d.base;
-      S = b - d.base;
-      if (b - a > SMAX || lo < 0 || S > 2 * SMAX) {
-        atomicOr(err, 1u | 16u);
-        lo = max(min(lo, 2 * SMAX), 0);
-        S = max(min(S, 2 * SMAX), lo);
-      }
-    } else {
-      d.base = fb != HZ ? fb : 0;
-    }
-    d.S = S;
-    d.nt0 = lo / TQ;
-    d.NT = (nd + S + TQ - 1) / TQ - d.nt0;
-    const int MT = (nd + TQ - 1) / TQ;
-    const int m0 = max(fs[f].mlo, 0) / TQ;
-    const int m1 = min(fs[f].mhi, nd - 1) / TQ;
-    d.mt0 = m0 < MT ? m0 : 0;
-    d.MTf = m1 >= m0 && m0 < MT ? min(m1, MT - 1) - m0 + 1 : MT;
-    fd[f] = d;
+    lds_put(fd + f, make_desc(lds_get(fs + f), a, b, nd, err));
   }
   if (tid == 0 && !fits) atomicOr(err, 8u);  // table too small: never expected
   __syncthreads();
