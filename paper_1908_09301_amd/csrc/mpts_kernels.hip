@@ -337,6 +337,7 @@ struct Carve {
   FrameSrc *fs;        // NFR frames of an index, then the 2 early Cauchy frames of the next
   FrameD *fd;          // the same
   int *red;            // 64
+  int *geo;            // geometry of the late frames (LG_WORDS)
   unsigned long long *tmark;  // phase timer: time of the last mark
   int *span;           // 2 NFR column ranges of this workgroup, then 4 of the early frames
   int *hc;             // exponent caches: [3][N+1] coefficient rows, NCONST constants, then
@@ -366,6 +367,8 @@ __device__ Carve carve(unsigned char *smem, const Inst &I) {
   p += sizeof(FrameD) * (NFR + 2);
   c.red = (int *)p;
   p += 64 * 4;
+  c.geo = (int *)p;
+  p += 32 * 4;
   c.tmark = (unsigned long long *)p;
   p += 8;
   c.span = (int *)p;
@@ -395,7 +398,7 @@ __device__ __forceinline__ void prof_mark(const Inst &I, const Carve &cv, int ph
 size_t lds_bytes(int L, int N, int RS, int WB, int CM, bool adjoint) {
   const int NV = (L + 2 + 3) & ~3;
   size_t b = (size_t)NFR * WB * 8 + (size_t)3 * 64 * CM * 8 + (size_t)6 * (NV > RS ? NV : RS) * 4 +
-             (size_t)4 * RS * 4 + sizeof(FrameSrc) * (NFR + 2) + sizeof(FrameD) * (NFR + 2) + 64 * 4 +
+             (size_t)4 * RS * 4 + sizeof(FrameSrc) * (NFR + 2) + sizeof(FrameD) * (NFR + 2) + 96 * 4 +
              8 + 4 * NFR * 4 + ((size_t)3 * (N + 1) + 3 * NCONST) * 4 +
              (adjoint ? (size_t)adj_table_bytes(N) : 0);
   return (b + 255) & ~(size_t)255;
@@ -429,6 +432,15 @@ __device__ __forceinline__ void copy_norm(const int32_t *src, int32_t *dst, int 
 
 // Wave 0 of the leader: spin until the NSPLIT arrival counters (one per
 // 128-byte line) sum to at least target; gives up like spin_until.
+// A spin gives up when its own poll budget runs out or, checked now and
+// then, when another workgroup has already given up (error bit 4): then
+// every wait of the launch ends quickly and the host reports the timeout.
+__device__ __forceinline__ bool spin_abandoned(long long polls, const uint32_t *err) {
+  if (polls > (1LL << 25)) return true;
+  if ((polls & 1023) != 0) return false;
+  return (__builtin_amdgcn_raw_buffer_load_b32(dev_rsrc(err, 4), 0, 0, 16) & 4u) != 0;
+}
+
 __device__ void spin_until_sum(uint32_t *ctr, uint32_t target, uint32_t *err) {
   const int lane = threadIdx.x & 63;
   const __amdgpu_buffer_rsrc_t rs = dev_rsrc(ctr, NSPLIT * 128);
@@ -440,7 +452,7 @@ __device__ void spin_until_sum(uint32_t *ctr, uint32_t target, uint32_t *err) {
     for (int o = 1; o < NSPLIT; o <<= 1) v += __shfl_xor(v, o, 64);
     if (__shfl(v, 0, 64) >= target) break;
     __builtin_amdgcn_s_sleep(2);
-    if (++polls > (1LL << 25)) {
+    if (spin_abandoned(++polls, err)) {
       if (lane == 0) atomicOr(err, 4u);
       break;
     }
@@ -456,7 +468,7 @@ __device__ void spin_until(uint32_t *flag, uint32_t target, uint32_t *err) {
   const __amdgpu_buffer_rsrc_t rs = dev_rsrc(flag, 4);
   while ((uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, 0, 0, 16) < target) {
     __builtin_amdgcn_s_sleep(2);
-    if (++polls > (1LL << 25)) {
+    if (spin_abandoned(++polls, err)) {
       atomicOr(err, 4u);
       break;
     }
@@ -530,7 +542,8 @@ __device__ void finalize_task(const Inst &I, const Carve &cv, int which, int i,
 // Group protocol: one coefficient (or adjoint) index at a time.
 struct GroupSync {
   uint32_t gen;
-  unsigned long long nbulk;
+  unsigned long long nbulk;    // rounds of group frames so far (their parity picks the buffer)
+  unsigned long long arrived;  // arrivals the leader has waited for so far
 };
 
 // Leader: after writing rows that the group will read, publish them.
@@ -555,38 +568,17 @@ __device__ void group_publish(const Inst &I, bool leader, GroupSync &gs, uint32_
 // its columns into the group's global frames.  The leader then waits for
 // every workgroup's adds.  Returns the frames the leader finalises from.
 __device__ const long long *group_bulk(const Inst &I, const Carve &cv, int nf, int rank,
-                                       GroupSync &gs, uint32_t *err, bool merge_early = false,
-                                       bool few = false) {
+                                       GroupSync &gs, uint32_t *err) {
   const int tid = threadIdx.x;
   const int G = I.G, WB = I.WB;
-  if (few) {
-    // every frame has a few cached terms: one thread per frame
-    frame_setup_few(cv.fs, cv.fd, nf, I.nd, I.RS, err);
-    __syncthreads();
-  } else {
-    frame_setup(cv.fs, cv.fd, nf, I.nd, I.RS, cv.red, cv.offs, cv.maxn, (int *)cv.tcols,
-                3 * 64 * I.CM * 2, err);
-  }
+  frame_setup(cv.fs, cv.fd, nf, I.nd, I.RS, cv.red, cv.offs, cv.maxn, (int *)cv.tcols,
+              3 * 64 * I.CM * 2, err);
   prof_mark(I, cv, PH_SETUP);
   frames_accumulate(cv.fs, cv.fd, nf, I.nd, I.RS, WB, cv.lf, rank, G, cv.span);
   __syncthreads();
-  if (merge_early && tid < 2) {
-    // frames 0 and 1 also hold this workgroup's early products
-    int *sp = cv.span + 2 * tid;
-    const int *es = cv.span + 2 * NFR + 2 * tid;
-    if (es[0] < es[1]) {
-      if (sp[0] < sp[1]) {
-        sp[0] = min(sp[0], es[0]);
-        sp[1] = max(sp[1], es[1]);
-      } else {
-        sp[0] = es[0];
-        sp[1] = es[1];
-      }
-    }
-  }
-  if (merge_early) __syncthreads();
   prof_mark(I, cv, PH_ACCUM);
   ++gs.nbulk;
+  gs.arrived += (unsigned long long)G;
   long long *gf = I.gframes + (size_t)(gs.nbulk & 1) * NFR * WB;
   if (G == 1) return cv.lf;
   for (int f = 0; f < nf; ++f) {
@@ -607,7 +599,7 @@ __device__ const long long *group_bulk(const Inst &I, const Carve &cv, int nf, i
     __hip_atomic_fetch_add(I.sync + SY_ARRIVE + 32 * (rank % NSPLIT), 1u, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
   if (rank == 0) {
-    if (tid < 64) spin_until_sum(I.sync + SY_ARRIVE, (uint32_t)(G * gs.nbulk), err);
+    if (tid < 64) spin_until_sum(I.sync + SY_ARRIVE, (uint32_t)gs.arrived, err);
     __syncthreads();
     prof_mark(I, cv, PH_WAIT);
   }
@@ -671,7 +663,7 @@ __device__ void spin_hdr(const uint32_t *line, uint32_t gen, int *vals, uint32_t
       return;
     }
     __builtin_amdgcn_s_sleep(2);
-    if (++polls > (1LL << 25)) {
+    if (spin_abandoned(++polls, err)) {
       atomicOr(err, 4u);
       for (int j = 0; j < 6; ++j) vals[j] = 0;
       return;
@@ -706,7 +698,7 @@ __device__ void release_rows(const Inst &I, const Carve &cv, bool leader,
       const l_i32 *row = (const l_i32 *)(cv.trow + (size_t)(2 * task + 1) * RS);
       hc_row(I, cv, tid)[i + 1] = row[1] != 0 ? row[0] : HZ;
     }
-    clear_frames(I, cv, NFR, frames);
+    if (frames) clear_frames(I, cv, NFR, frames);
     __syncthreads();
   } else {
     ++gs.gen;
@@ -790,95 +782,354 @@ __device__ __forceinline__ int cauchy_base(const int *hU, const int *hV, int i) 
   return e == HZ ? HZ : e - SMAX;
 }
 
+// ---------------------------------------------------------------------------
+// The late frames of index i: the products with the newest rows i.
+//   frame 0: a_i g_0 + a_0 g_i (the terms k = 0 and k = i of sum_k a_{i-k} g_k)
+//   frame 1: a_i b_0 + a_0 b_i
+//   frame 2: sigma b_i + (-sigma) a_i
+//   frame 3: R a_i
+//   frame 4: (-b) g_i
+// (index 0: frames 0 and 1 hold the single term a_0 g_0, a_0 b_0).  The U
+// operand gives the tile rows, the V operand the tile columns, read shifted
+// by the term's offset from the frame base, so that a tile's 16 output
+// columns do not depend on the offset.
+
+// Largest term offset of late frame f: the Cauchy frames take their base
+// SMAX below their first old term, the two terms of frame 2 spread over at
+// most SMAX digits, and the single products have none.
+enum { LG_N = 0, LG_MT0 = NFR, LG_MTF = 2 * NFR, LG_NT = 3 * NFR, LG_PRE = 4 * NFR,
+       LG_WORDS = 5 * NFR + 1 };
+static_assert(LG_WORDS <= 32, "late geometry fits its LDS words");
+
+__device__ __forceinline__ int late_smax(int f) { return f < 2 ? 2 * SMAX : f == 2 ? SMAX : 0; }
+
+// Geometry of the late frames in cv.geo, fixed for the launch (thread 0,
+// after the constants' digit spans): terms per frame, tile rows [mt0, mt0 +
+// MTf) holding the U operands' nonzero digits (the constants are often
+// short), tile columns [0, NT) covering the largest offset, and the prefix
+// sums of the (tile, term) items, which the followers deal among themselves.
+__device__ void late_geometry(const Inst &I, const Carve &cv) {
+  if (threadIdx.x != 0) return;
+  const int nd = I.nd, MT = (nd + TQ - 1) / TQ;
+  l_i32 *g = (l_i32 *)cv.geo;
+  int pre = 0;
+  for (int f = 0; f < NFR; ++f) {
+    int lo = 0, hi = nd - 1;
+    if (f == 2) {
+      lo = min(hc_span(I, cv, C_SIGMA)[0], hc_span(I, cv, C_NSIGMA)[0]);
+      hi = max(hc_span(I, cv, C_SIGMA)[1], hc_span(I, cv, C_NSIGMA)[1]);
+    } else if (f >= 3) {
+      const int c = f == 3 ? C_R : C_NB;
+      lo = hc_span(I, cv, c)[0];
+      hi = hc_span(I, cv, c)[1];
+    }
+    const int m0 = max(lo, 0) / TQ, m1 = min(hi, nd - 1) / TQ;
+    const bool ok = m1 >= m0 && m0 < MT;
+    g[LG_N + f] = f < 3 ? 2 : 1;
+    g[LG_MT0 + f] = ok ? m0 : 0;
+    g[LG_MTF + f] = ok ? min(m1, MT - 1) - m0 + 1 : MT;
+    g[LG_NT + f] = (nd + late_smax(f) + TQ - 1) / TQ;
+    g[LG_PRE + f] = pre;
+    pre += g[LG_MTF + f] * g[LG_NT + f] * g[LG_N + f];
+  }
+  g[LG_PRE + NFR] = pre;
+}
+
+// Operands and exponents of term k of late frame f at index i.
+__device__ __forceinline__ void late_term(const Inst &I, const Carve &cv, int f, int k, int i,
+                                          const int32_t **U, const int32_t **V, int *eu,
+                                          int *ev) {
+  const l_i32 *ha = (const l_i32 *)hc_row(I, cv, 0), *hb = (const l_i32 *)hc_row(I, cv, 1),
+              *hg = (const l_i32 *)hc_row(I, cv, 2);
+  auto cst = [&](int c) { return (const int32_t *)(I.consts + (size_t)c * I.RS); };
+  auto hcst = [&](int c) { return ((const l_i32 *)hc_const(I, cv, c))[0]; };
+  if (f < 2) {
+    const int arr = f == 0 ? 2 : 1;
+    const l_i32 *hv = f == 0 ? hg : hb;
+    const int iu = k == 0 ? i : 0, iv = k == 0 ? 0 : i;
+    *U = row_ptr(I, 0, iu);
+    *V = row_ptr(I, arr, iv);
+    *eu = ha[iu];
+    *ev = hv[iv];
+  } else if (f == 2) {
+    const int c = k == 0 ? C_SIGMA : C_NSIGMA;
+    *U = cst(c);
+    *V = row_ptr(I, k == 0 ? 1 : 0, i);
+    *eu = hcst(c);
+    *ev = k == 0 ? hb[i] : ha[i];
+  } else {
+    const int c = f == 3 ? C_R : C_NB;
+    *U = cst(c);
+    *V = row_ptr(I, f == 3 ? 0 : 2, i);
+    *eu = hcst(c);
+    *ev = f == 3 ? ha[i] : hg[i];
+  }
+}
+
+__device__ __forceinline__ int esum2(int eu, int ev) { return (eu == HZ || ev == HZ) ? HZ : eu + ev; }
+
+__device__ __forceinline__ int late_nterms(int f, int i) { return f < 2 ? (i == 0 ? 1 : 2) : f == 2 ? 2 : 1; }
+
+// Exponent base of late frame f at index i: the Cauchy frames' given base,
+// else the smallest exponent sum of the frame's nonzero terms (HZ: none).
+__device__ int late_base(const Inst &I, const Carve &cv, int f, int i) {
+  if (f < 2) return cauchy_base(hc_row(I, cv, 0), hc_row(I, cv, f == 0 ? 2 : 1), i);
+  int b = 0x7fffffff;
+  for (int k = 0; k < late_nterms(f, i); ++k) {
+    const int32_t *U, *V;
+    int eu, ev;
+    late_term(I, cv, f, k, i, &U, &V, &eu, &ev);
+    const int e = esum2(eu, ev);
+    if (e != HZ) b = min(b, e);
+  }
+  return b == 0x7fffffff ? HZ : b;
+}
+
+// Leader: descriptor of frame f of index i as finalised (early and late
+// terms together).  The Cauchy frames span every offset in [0, 2 SMAX] from
+// their given base; the others are set up from their terms.
+__device__ FrameD late_desc(const Inst &I, const Carve &cv, int f, int i, uint32_t *err) {
+  int a = 0x7fffffff, b = -0x7fffffff;
+  const int n = late_nterms(f, i);
+  for (int k = 0; k < n; ++k) {
+    const int32_t *U, *V;
+    int eu, ev;
+    late_term(I, cv, f, k, i, &U, &V, &eu, &ev);
+    const int e = esum2(eu, ev);
+    if (e != HZ) {
+      a = min(a, e);
+      b = max(b, e);
+    }
+  }
+  const int fb = f < 2 ? late_base(I, cv, f, i) : HZ;
+  FrameD d = make_desc(n, fb, 0, 0x7fffffff, a, b, I.nd, err);
+  if (f < 2 && fb != HZ) {
+    d.nz = 1;
+    d.base = fb;
+    d.nt0 = 0;
+    d.S = 2 * SMAX;
+    d.NT = (I.nd + 2 * SMAX + TQ - 1) / TQ;
+  }
+  return d;
+}
+
+// Follower: this workgroup's share of the late products of index i (a
+// contiguous range of the items, one per thread in the usual case) into its
+// LDS frames, then the columns it holds (with the early products of frames
+// 0 and 1 of this index, accumulated there before) added into the group's
+// frames in global memory, then its arrival.
+__device__ void late_step(const Inst &I, const Carve &cv, int rank, int i, GroupSync &gs) {
+  const int tid = threadIdx.x, WB = I.WB;
+  const l_i32 *g = (const l_i32 *)cv.geo;
+  l_i32 *span = (l_i32 *)cv.span;
+  const unsigned total = (unsigned)g[LG_PRE + NFR];
+  const unsigned W = (unsigned)(I.G - 1), r = (unsigned)(rank - 1);
+  const unsigned lo = (unsigned)(((unsigned long long)total * r) / W);
+  const unsigned hi = (unsigned)(((unsigned long long)total * (r + 1)) / W);
+  if (tid < NFR) {
+    // columns of this workgroup's tiles of frame f (whole anti-diagonals)
+    const int f = tid;
+    const unsigned p0 = (unsigned)g[LG_PRE + f], p1 = (unsigned)g[LG_PRE + f + 1];
+    const unsigned a = max(lo, p0), b = min(hi, p1);
+    int c0 = 0, c1 = 0;
+    if (a < b) {
+      const int n = g[LG_N + f], MTf = g[LG_MTF + f], NT = g[LG_NT + f], mt0 = g[LG_MT0 + f];
+      int mt, nt;
+      tile_coords((int)((a - p0) / n), MTf, NT, &mt, &nt);
+      const int d0 = mt + nt;
+      tile_coords((int)((b - 1 - p0) / n), MTf, NT, &mt, &nt);
+      const int d1 = mt + nt;
+      c0 = (min(d0, d1) + mt0) * TQ;
+      c1 = (max(d0, d1) + mt0) * TQ + 2 * TQ;
+    }
+    if (f < 2) {
+      // frames 0 and 1 also hold the early products (then forget their range)
+      l_i32 *es = span + 2 * NFR + 2 * f;
+      if (es[0] < es[1]) {
+        if (c0 < c1) {
+          c0 = min(c0, (int)es[0]);
+          c1 = max(c1, (int)es[1]);
+        } else {
+          c0 = es[0];
+          c1 = es[1];
+        }
+      }
+      es[0] = 0;
+      es[1] = 0;
+    }
+    span[2 * f] = c0;
+    span[2 * f + 1] = c1;
+  }
+  for (unsigned q = lo + tid; q < hi; q += WGS) {
+    int f = 0;
+    while (f < NFR - 1 && q >= (unsigned)g[LG_PRE + f + 1]) ++f;
+    const unsigned rel = q - (unsigned)g[LG_PRE + f];
+    const bool two = g[LG_N + f] == 2;
+    const int t = (int)(two ? rel >> 1 : rel), k = (int)(two ? rel & 1u : 0u);
+    if (k >= late_nterms(f, i)) continue;
+    int mt, nt;
+    tile_coords(t, g[LG_MTF + f], g[LG_NT + f], &mt, &nt);
+    mt += g[LG_MT0 + f];
+    const int32_t *U, *V;
+    int eu, ev;
+    late_term(I, cv, f, k, i, &U, &V, &eu, &ev);
+    const int base = late_base(I, cv, f, i);
+    const int e = esum2(eu, ev);
+    const int off = (e == HZ || base == HZ) ? 0 : min(max(e - base, 0), late_smax(f));
+    int32_t uu[TQ], vv[TQ];
+    tile_load_g(uu, vv, (const g_i32 *)U, (const g_i32 *)V, mt, nt, off);
+    long long acc[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[j] = 0;
+    tile_fma(acc, uu, vv);
+    acc_flush(acc, cv.lf + (size_t)f * WB + (mt + nt) * TQ);
+  }
+  __syncthreads();
+  prof_mark(I, cv, PH_ACCUM);
+  ++gs.nbulk;
+  gs.arrived += (unsigned long long)(I.G - 1);
+  long long *gf = I.gframes + (size_t)(gs.nbulk & 1) * NFR * WB;
+  for (int f = 0; f < NFR; ++f) {
+    const int c0 = span[2 * f], c1 = span[2 * f + 1];
+    for (int c = c0 + tid; c < c1; c += WGS) {
+      l_i64 *lc = (l_i64 *)cv.lf + (size_t)f * WB + c;
+      const long long v = *lc;
+      if (v != 0) {
+        __hip_atomic_fetch_add((unsigned long long *)(gf + (size_t)f * WB + c),
+                               (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        *lc = 0;
+      }
+    }
+  }
+  wait_vmem();
+  __syncthreads();
+  if (tid == 0)
+    __hip_atomic_fetch_add(I.sync + SY_ARRIVE + 32 * (rank % NSPLIT), 1u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+  prof_mark(I, cv, PH_FLUSH);
+}
+
 // The Taylor coefficients 1..N of one step (equation (3)), rows 0 given.
 //
-// With two or more workgroups the Cauchy sums are computed one index ahead:
-// while the leader finalises index i, every other workgroup accumulates the
-// terms of the Cauchy sums of index i+1 that involve no row i+1 (k = 1..i)
-// into its LDS frames.  Once rows i+1 are published, the products with them
-// (k = 0 and k = i+1, and the three single-product frames) are dealt over the
-// whole group, and the frames go to the leader as before.  Both parts use
-// the frame base of cauchy_base, which needs no row i+1.
+// One workgroup: every frame of index i in LDS, then the three
+// finalisation tasks.
+//
+// Two or more: the leader (workgroup 0) only finalises.  The Cauchy sums
+// are computed one index ahead: while the leader finalises index i, every
+// follower accumulates its share of the terms of the Cauchy sums of index
+// i+1 that involve no row i+1 (k = 1..i) into its LDS frames.  Once rows
+// i+1 are published, the followers deal the late products among themselves
+// (late_step), add their columns into the group's frames and arrive; the
+// leader waits for them, finalises index i+1 from the group's frames and
+// publishes rows i+2.  The early and late parts of a Cauchy frame share the
+// base of cauchy_base, which needs no row i+1.  The leader clears each
+// index's group frames while it waits for the next index's arrivals.
 template <int CM>
 __device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, GroupSync &gs,
                                      const int32_t *state, uint32_t *err) {
   const int tid = threadIdx.x, wave = tid >> 6;
   const bool leader = rank == 0;
-  const int RS = I.RS, nd = I.nd;
-  const bool look = I.G >= 2;
+  const int RS = I.RS, nd = I.nd, WB = I.WB;
+  (void)state;
   // the beta task keeps b_i in LDS (its result row): start with the row b_0
   if (leader && wave == 0) {
     const g_i32 *b0 = (const g_i32 *)row_ptr(I, 1, 0);
     l_i32 *dst = (l_i32 *)(cv.trow + RS);
     for (int w = threadIdx.x & 63; w < RS; w += 64) dst[w] = b0[w];
   }
-  (void)state;
   const int *ha = hc_row(I, cv, 0), *hb = hc_row(I, cv, 1), *hg = hc_row(I, cv, 2);
-  auto cst = [&](int c) { return I.consts + (size_t)c * RS; };
-  int eb0 = HZ, eb1 = HZ;  // thread 0: bases of the two Cauchy frames of index i
-  for (int i = 0; i < I.N; ++i) {
-    if (tid == 0) {
-      FrameSrc fs[NFR];  // built in registers, stored to LDS below
-      eb0 = cauchy_base(ha, hg, i);
-      eb1 = cauchy_base(ha, hb, i);
-      if (look) {
-        // the terms with the newest rows (rows i); the others were taken early
-        if (i == 0) {
-          fs[0] = mk_frame1(mk_part(PK_ONE, 1, 0, row_ptr(I, 0, 0), row_ptr(I, 2, 0), ha, hg));
-          fs[1] = mk_frame1(mk_part(PK_ONE, 1, 0, row_ptr(I, 0, 0), row_ptr(I, 1, 0), ha, hb));
-        } else {
-          fs[0] = mk_frame2(mk_part(PK_ONE, 1, 0, row_ptr(I, 0, i), row_ptr(I, 2, 0), ha + i, hg),
-                            mk_part(PK_ONE, 1, 0, row_ptr(I, 0, 0), row_ptr(I, 2, i), ha, hg + i));
-          fs[1] = mk_frame2(mk_part(PK_ONE, 1, 0, row_ptr(I, 0, i), row_ptr(I, 1, 0), ha + i, hb),
-                            mk_part(PK_ONE, 1, 0, row_ptr(I, 0, 0), row_ptr(I, 1, i), ha, hb + i));
-        }
-      } else {
+  if (I.G == 1) {
+    auto cst = [&](int c) { return I.consts + (size_t)c * RS; };
+    for (int i = 0; i < I.N; ++i) {
+      if (tid == 0) {
+        FrameSrc fs[NFR];  // built in registers, stored to LDS below
         fs[0] = mk_frame1(mk_part(PK_CAUCHY, i + 1, i, row_ptr(I, 0, 0), row_ptr(I, 2, 0), ha, hg));
         fs[1] = mk_frame1(mk_part(PK_CAUCHY, i + 1, i, row_ptr(I, 0, 0), row_ptr(I, 1, 0), ha, hb));
-      }
-      fs[0].fbase = eb0;
-      fs[1].fbase = eb1;
-      fs[2] = mk_frame2(mk_part(PK_ONE, 1, 0, cst(C_SIGMA), row_ptr(I, 1, i),
-                                hc_const(I, cv, C_SIGMA), hb + i),
-                        mk_part(PK_ONE, 1, 0, cst(C_NSIGMA), row_ptr(I, 0, i),
-                                hc_const(I, cv, C_NSIGMA), ha + i));
-      fs[3] = mk_frame1(mk_part(PK_ONE, 1, 0, cst(C_R), row_ptr(I, 0, i), hc_const(I, cv, C_R),
-                                ha + i));
-      // sigma and R are often short: only their nonzero digit rows take tiles
-      fs[2].mlo = min(hc_span(I, cv, C_SIGMA)[0], hc_span(I, cv, C_NSIGMA)[0]);
-      fs[2].mhi = max(hc_span(I, cv, C_SIGMA)[1], hc_span(I, cv, C_NSIGMA)[1]);
-      fs[3].mlo = hc_span(I, cv, C_R)[0];
-      fs[3].mhi = hc_span(I, cv, C_R)[1];
-      fs[4] = mk_frame1(mk_part(PK_ONE, 1, 0, cst(C_NB), row_ptr(I, 2, i), hc_const(I, cv, C_NB),
-                                hg + i));
+        fs[0].fbase = cauchy_base(ha, hg, i);
+        fs[1].fbase = cauchy_base(ha, hb, i);
+        fs[2] = mk_frame2(mk_part(PK_ONE, 1, 0, cst(C_SIGMA), row_ptr(I, 1, i),
+                                  hc_const(I, cv, C_SIGMA), hb + i),
+                          mk_part(PK_ONE, 1, 0, cst(C_NSIGMA), row_ptr(I, 0, i),
+                                  hc_const(I, cv, C_NSIGMA), ha + i));
+        fs[3] = mk_frame1(mk_part(PK_ONE, 1, 0, cst(C_R), row_ptr(I, 0, i),
+                                  hc_const(I, cv, C_R), ha + i));
+        // sigma and R are often short: only their nonzero digit rows take tiles
+        fs[2].mlo = min(hc_span(I, cv, C_SIGMA)[0], hc_span(I, cv, C_NSIGMA)[0]);
+        fs[2].mhi = max(hc_span(I, cv, C_SIGMA)[1], hc_span(I, cv, C_NSIGMA)[1]);
+        fs[3].mlo = hc_span(I, cv, C_R)[0];
+        fs[3].mhi = hc_span(I, cv, C_R)[1];
+        fs[4] = mk_frame1(mk_part(PK_ONE, 1, 0, cst(C_NB), row_ptr(I, 2, i),
+                                  hc_const(I, cv, C_NB), hg + i));
 #pragma unroll
-      for (int f = 0; f < NFR; ++f) lds_put(cv.fs + f, fs[f]);
-    }
-    __syncthreads();
-    prof_mark(I, cv, PH_BUILD);
-    const long long *frames =
-        group_bulk(I, cv, NFR, rank, gs, err, look && !leader && i >= 2, look);
-    if (leader) {
-      // frames 0 and 1 as finalised: from their base, wide enough for every
-      // offset in [0, 2 SMAX]
-      if (tid == 0) {
-        const int eb[2] = {eb0, eb1};
-        for (int f = 0; f < 2; ++f) {
-          if (eb[f] == HZ) continue;
-          FrameD d = cv.fd[f];
+        for (int f = 0; f < NFR; ++f) lds_put(cv.fs + f, fs[f]);
+      }
+      __syncthreads();
+      const long long *frames = group_bulk(I, cv, NFR, rank, gs, err);
+      if (tid < 2) {
+        // frames 0 and 1 as finalised: from their base, wide enough for
+        // every offset in [0, 2 SMAX]
+        const int eb = cauchy_base(ha, tid == 0 ? hg : hb, i);
+        if (eb != HZ) {
+          FrameD d = lds_get(cv.fd + tid);
           d.nz = 1;
-          d.base = eb[f];
+          d.base = eb;
           d.nt0 = 0;
           d.S = 2 * SMAX;
           d.NT = (nd + 2 * SMAX + TQ - 1) / TQ;
-          cv.fd[f] = d;
+          lds_put(cv.fd + tid, d);
         }
       }
       __syncthreads();
-      if (wave < 3) finalize_task<CM>(I, cv, wave, i, frames, I.G > 1, err);
+      if (wave < 3) finalize_task<CM>(I, cv, wave, i, frames, false, err);
       __syncthreads();
       prof_mark(I, cv, PH_FINAL);
-    } else if (look && i + 1 < I.N && i + 1 >= 2) {
+      release_rows(I, cv, true, frames, gs, i, err);
+      prof_mark(I, cv, PH_CLEAR);
+    }
+    return;
+  }
+  if (leader) {
+    l_i32 *ccols = (l_i32 *)cv.span;  // column counts of the frames still to clear
+    const long long *pend = nullptr;  // the previous index's group frames
+    for (int i = 0; i < I.N; ++i) {
+      if (tid < NFR) lds_put(cv.fd + tid, late_desc(I, cv, tid, i, err));
+      if (pend && wave > 0) {
+        for (int f = 0; f < NFR; ++f) {
+          long long *fr = const_cast<long long *>(pend) + (size_t)f * WB;
+          const int nc = ccols[f];
+          for (int c = tid - 64; c < nc; c += WGS - 64) st_relaxed(fr + c, 0LL);
+        }
+      }
+      prof_mark(I, cv, PH_SETUP);
+      ++gs.nbulk;
+      gs.arrived += (unsigned long long)(I.G - 1);
+      if (tid < 64) spin_until_sum(I.sync + SY_ARRIVE, (uint32_t)gs.arrived, err);
+      __syncthreads();
+      prof_mark(I, cv, PH_WAIT);
+      const long long *frames = I.gframes + (size_t)(gs.nbulk & 1) * NFR * WB;
+      if (wave < 3) finalize_task<CM>(I, cv, wave, i, frames, true, err);
+      __syncthreads();
+      prof_mark(I, cv, PH_FINAL);
+      if (tid < NFR) ccols[tid] = cv.fd[tid].nz ? frame_cols(cv.fd[tid], nd) : 0;
+      pend = frames;
+      release_rows(I, cv, true, nullptr, gs, i, err);
+      prof_mark(I, cv, PH_CLEAR);
+    }
+    // the last index's frames: the wait before the group's next publication
+    // covers these stores
+    if (pend) {
+      for (int f = 0; f < NFR; ++f) {
+        long long *fr = const_cast<long long *>(pend) + (size_t)f * WB;
+        const int nc = ccols[f];
+        for (int c = tid; c < nc; c += WGS) st_relaxed(fr + c, 0LL);
+      }
+    }
+    __syncthreads();
+    return;
+  }
+  for (int i = 0; i < I.N; ++i) {
+    late_step(I, cv, rank, i, gs);
+    if (i + 1 < I.N && i + 1 >= 2) {
       // early part of index j = i+1: Cauchy terms k = 1..j-1 (rows <= i)
       const int j = i + 1;
       if (tid == 0) {
@@ -901,7 +1152,7 @@ __device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, G
       __syncthreads();
       prof_mark(I, cv, PH_FINAL);
     }
-    release_rows(I, cv, leader, frames, gs, i, err);
+    release_rows(I, cv, false, nullptr, gs, i, err);
     prof_mark(I, cv, PH_CLEAR);
   }
 }
@@ -988,6 +1239,9 @@ __global__ void __launch_bounds__(WGS) k_run(const Inst *__restrict__ insts,
       write_row(I.cnorm + (size_t)c * (L + 2), L, nd, RS, I.consts + (size_t)c * RS, G > 1, lane,
                 64);
   }
+  __syncthreads();
+  late_geometry(I, cv);
+  if (tid < 4 * NFR) cv.span[tid] = 0;
   __syncthreads();
 
   for (long long step = 0; step < I.nsteps; ++step) {
@@ -1100,6 +1354,9 @@ __global__ void __launch_bounds__(WGS) k_adj(const Inst *__restrict__ insts,
       for (int j = lane; j < L + 2; j += 64) pb[j] = 0;
     }
   }
+  __syncthreads();
+  late_geometry(I, cv);
+  if (tid < 4 * NFR) cv.span[tid] = 0;
   __syncthreads();
   const int32_t *cs = I.consts;
   for (long long n = I.nsteps - 1; n >= 0; --n) {

@@ -303,18 +303,19 @@ __device__ __forceinline__ void red_reset(int *red) {
   if (t < 2 * NFR) ((l_i32 *)red)[t] = (t & 1) ? -0x7fffffff : 0x7fffffff;
 }
 
-// Descriptor of a frame whose nonzero terms have exponent sums in [a, b]
-// (a > b: no nonzero term).  A given base must lie at most 2 SMAX below
-// every term; the spread of the terms is at most SMAX either way.
-__device__ __forceinline__ FrameD make_desc(const FrameSrc &src, int a, int b, int nd,
-                                           uint32_t *err) {
+// Descriptor of a frame of n terms whose nonzero terms have exponent sums
+// in [a, b] (a > b: no nonzero term), with the given base fbase (HZ: none)
+// and the U operands' nonzero digits in [mlo, mhi].  A given base must lie
+// at most 2 SMAX below every term; the spread of the terms is at most SMAX
+// either way.
+__device__ __forceinline__ FrameD make_desc(int n, int fbase, int mlo, int mhi, int a, int b,
+                                           int nd, uint32_t *err) {
   FrameD d;
-  d.n = src.n;
+  d.n = n;
   d.nz = (a <= b) ? 1 : 0;
-  const int fb = src.fbase;
   int lo = 0, S = 0;
   if (d.nz) {
-    d.base = fb != HZ ? fb : a;
+    d.base = fbase != HZ ? fbase : a;
     lo = a - d.base;
     S = b - d.base;
     if (b - a > SMAX || lo < 0 || S > 2 * SMAX) {
@@ -323,39 +324,17 @@ __device__ __forceinline__ FrameD make_desc(const FrameSrc &src, int a, int b, i
       S = max(min(S, 2 * SMAX), lo);
     }
   } else {
-    d.base = fb != HZ ? fb : 0;
+    d.base = fbase != HZ ? fbase : 0;
   }
   d.S = S;
   d.nt0 = lo / TQ;
   d.NT = (nd + S + TQ - 1) / TQ - d.nt0;
   const int MT = (nd + TQ - 1) / TQ;
-  const int m0 = max(src.mlo, 0) / TQ;
-  const int m1 = min(src.mhi, nd - 1) / TQ;
+  const int m0 = max(mlo, 0) / TQ;
+  const int m1 = min(mhi, nd - 1) / TQ;
   d.mt0 = m0 < MT ? m0 : 0;
   d.MTf = m1 >= m0 && m0 < MT ? min(m1, MT - 1) - m0 + 1 : MT;
   return d;
-}
-
-// Frame setup for frames of a few terms each, all with both exponent
-// caches (the products with the newest rows): thread f sets up frame f, no
-// workgroup reduction; the caller synchronises the workgroup afterwards.
-__device__ __forceinline__ void frame_setup_few(const FrameSrc *fs, FrameD *fd, int nf, int nd,
-                                                int RS, uint32_t *err) {
-  const int f = threadIdx.x;
-  if (f >= nf) return;
-  const int np = ((const l_i32 *)&fs[f].nparts)[0];
-  int a = 0x7fffffff, b = -0x7fffffff;
-  for (int j = 0; j < np; ++j) {
-    const FramePart q = lds_get(&fs[f].p[j]);
-    for (int k = 0; k < q.n; ++k) {
-      const int e = part_esum(q, k, RS);
-      if (e != HZ) {
-        a = min(a, e);
-        b = max(b, e);
-      }
-    }
-  }
-  lds_put(fd + f, make_desc(lds_get(fs + f), a, b, nd, err));
 }
 
 // Per-workgroup frame setup: exponent base and spread of each frame's
@@ -404,7 +383,8 @@ __device__ void frame_setup(FrameSrc *fs, FrameD *fd, int nf, int nd, int RS, in
   if (tid < nf) {
     const int f = tid;
     const int a = ((const l_i32 *)red)[2 * f], b = ((const l_i32 *)red)[2 * f + 1];
-    lds_put(fd + f, make_desc(lds_get(fs + f), a, b, nd, err));
+    const FrameSrc src = lds_get(fs + f);
+    lds_put(fd + f, make_desc(src.n, src.fbase, src.mlo, src.mhi, a, b, nd, err));
   }
   if (tid == 0 && !fits) atomicOr(err, 8u);  // table too small: never expected
   __syncthreads();
