@@ -82,7 +82,7 @@ struct Inst {
 
 // phases timed when Inst::prof is set (leader slots 0..15, one follower 16..31)
 enum { PH_SETUP = 0, PH_ACCUM, PH_FLUSH, PH_WAIT, PH_FINAL, PH_CLEAR, PH_HORNER, PH_STEP0,
-       PH_NPHASE = 16 };
+       PH_EBUILD, PH_ESETUP = 10, PH_NPHASE = 16 };
 constexpr int PROF_RANK = 8;  // per-workgroup profile words
 
 }  // namespace mpts

@@ -566,6 +566,10 @@ int read_status(mpts_ctx *c, void *ws, hipStream_t s) {
       for (int w2 = 0; w2 < 2; ++w2) {
         fprintf(stderr, w2 ? "\n  wg1:" : "\n  leader:");
         for (int j = 0; j < (w2 ? 8 : 16); ++j) fprintf(stderr, " %s=%.1f", nm[j], ph[w2 * PH_NPHASE + j] * us);
+        if (w2)
+          fprintf(stderr, " e.build=%.1f e.setup=%.1f e.part=%.1f e.slowest=%.1f",
+                  ph[PH_NPHASE + PH_EBUILD] * us, ph[PH_NPHASE + PH_ESETUP] * us,
+                  ph[PH_NPHASE + 9] * us, ph[PH_NPHASE + 11] * us);
       }
       fprintf(stderr, "\n");
       const int G = c->last_G;

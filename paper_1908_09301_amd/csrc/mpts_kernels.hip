@@ -1130,26 +1130,53 @@ __device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, G
   for (int i = 0; i < I.N; ++i) {
     late_step(I, cv, rank, i, gs);
     if (i + 1 < I.N && i + 1 >= 2) {
-      // early part of index j = i+1: Cauchy terms k = 1..j-1 (rows <= i)
+      // early part of index j = i+1: Cauchy terms k = 1..j-1 (rows <= i).
+      // Fixed descriptors: base SMAX below the first nonzero term, columns
+      // for every offset in [0, 2 SMAX] (as the leader finalises them).
       const int j = i + 1;
-      if (tid == 0) {
-        FrameSrc fs[2];
-        const int e0 = first_esum(ha, hg, j, 1, j - 1), e1 = first_esum(ha, hb, j, 1, j - 1);
-        fs[0] = mk_frame1(mk_part(PK_CAUCHY, j - 1, j - 1, row_ptr(I, 0, 0), row_ptr(I, 2, 1), ha,
-                                  hg + 1));
-        fs[1] = mk_frame1(mk_part(PK_CAUCHY, j - 1, j - 1, row_ptr(I, 0, 0), row_ptr(I, 1, 1), ha,
-                                  hb + 1));
-        fs[0].fbase = e0 == HZ ? HZ : e0 - SMAX;
-        fs[1].fbase = e1 == HZ ? HZ : e1 - SMAX;
-        lds_put(cv.fs + NFR, fs[0]);
-        lds_put(cv.fs + NFR + 1, fs[1]);
+      if (tid < 2) {
+        const int *hv = tid == 0 ? hg : hb;
+        const int e = first_esum(ha, hv, j, 1, j - 1);
+        FrameSrc fs = mk_frame1(mk_part(PK_CAUCHY, j - 1, j - 1, row_ptr(I, 0, 0),
+                                        row_ptr(I, tid == 0 ? 2 : 1, 1), ha, hv + 1));
+        fs.fbase = e == HZ ? HZ : e - SMAX;
+        lds_put(cv.fs + NFR + tid, fs);
+        FrameD d;
+        d.n = j - 1;
+        d.nz = e != HZ ? 1 : 0;
+        d.base = e == HZ ? 0 : e - SMAX;
+        d.S = 2 * SMAX;
+        d.nt0 = 0;
+        d.NT = (nd + 2 * SMAX + TQ - 1) / TQ;
+        d.mt0 = 0;
+        d.MTf = (nd + TQ - 1) / TQ;
+        lds_put(cv.fd + NFR + tid, d);
       }
       __syncthreads();
-      frame_setup(cv.fs + NFR, cv.fd + NFR, 2, nd, RS, cv.red, cv.offs, cv.maxn, (int *)cv.tcols,
-                  3 * 64 * I.CM * 2, err);
+      prof_mark(I, cv, PH_EBUILD);
+      {
+        // every term must lie in its frame's window (else the sum is not
+        // exact: reported through the error word, no barrier needed)
+        const int b0 = cv.fd[NFR].base, b1 = cv.fd[NFR + 1].base;
+        const l_i32 *la = (const l_i32 *)ha, *lg = (const l_i32 *)hg, *lb = (const l_i32 *)hb;
+        for (int t = tid; t < 2 * (j - 1); t += WGS) {
+          const int f = t >= j - 1 ? 1 : 0;
+          const int k = t - f * (j - 1) + 1;
+          const int e = esum2(la[j - k], f == 0 ? lg[k] : lb[k]);
+          const int base = f == 0 ? b0 : b1;
+          if (e != HZ && (e < base || e > base + 2 * SMAX)) atomicOr(err, 1u | 16u);
+        }
+      }
+      prof_mark(I, cv, PH_ESETUP);
+      unsigned long long *tp = I.prof && rank == 1 ? I.prof + PH_NPHASE + 9 : nullptr;
+      unsigned long long *tmx = (unsigned long long *)(cv.red + 32);
       frames_accumulate(cv.fs + NFR, cv.fd + NFR, 2, nd, RS, I.WB, cv.lf, rank, I.G,
-                        cv.span + 2 * NFR, true);
+                        cv.span + 2 * NFR, true, tp, tmx);
       __syncthreads();
+      if (tp && tid == 0) {
+        atomicAdd(tp + 2, *tmx);  // slowest thread's products
+        *tmx = 0;
+      }
       prof_mark(I, cv, PH_FINAL);
     }
     release_rows(I, cv, false, nullptr, gs, i, err);
@@ -1242,6 +1269,7 @@ __global__ void __launch_bounds__(WGS) k_run(const Inst *__restrict__ insts,
   __syncthreads();
   late_geometry(I, cv);
   if (tid < 4 * NFR) cv.span[tid] = 0;
+  if (tid == 0) *(unsigned long long *)(cv.red + 32) = 0;
   __syncthreads();
 
   for (long long step = 0; step < I.nsteps; ++step) {

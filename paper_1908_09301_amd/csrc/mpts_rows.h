@@ -544,8 +544,10 @@ __device__ __forceinline__ void part_tile_terms(long long (&acc)[16], const Fram
 // this workgroup touched in frame f (empty: lo >= hi).
 __device__ void frames_accumulate(const FrameSrc *fs_, const FrameD *fd_, int nf, int nd, int RS,
                                   int WB, long long *lf, int rank, int G, int *span_,
-                                  bool skip0 = false) {
+                                  bool skip0 = false, unsigned long long *tprof = nullptr,
+                                  unsigned long long *tmax = nullptr) {
   const int tid = threadIdx.x;
+  const unsigned long long tp0 = tprof ? wall_clock64() : 0;
   // the descriptors live in LDS: read them as such (no flat accesses here)
   const l_FrameSrc *fs = (const l_FrameSrc *)fs_;
   const l_FrameD *fd = (const l_FrameD *)fd_;
@@ -622,6 +624,11 @@ __device__ void frames_accumulate(const FrameSrc *fs_, const FrameD *fd_, int nf
   }
   if (tid < 2 * nf) span[tid] = 0;
   __syncthreads();
+  unsigned long long tp1 = 0;
+  if (tprof) {
+    tp1 = wall_clock64();
+    if (tid == 0) atomicAdd(tprof, tp1 - tp0);  // partition (thread 0)
+  }
   if (skip0 && rank == 0) return;
   if (tid < nf) {
     const int f = tid;
@@ -694,6 +701,9 @@ __device__ void frames_accumulate(const FrameSrc *fs_, const FrameD *fd_, int nf
     q = seg_end;
   }
   if (cur_f >= 0) acc_flush(acc, lf + (size_t)cur_f * WB + cur_d * TQ);
+  if (tprof)
+    __hip_atomic_fetch_max((unsigned long long __attribute__((address_space(3))) *)tmax,
+                           wall_clock64() - tp1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // One-term frames f = 0..nf-1 whose two rows are in LDS (the Horner
