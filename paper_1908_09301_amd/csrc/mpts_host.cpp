@@ -561,7 +561,7 @@ int read_status(mpts_ctx *c, void *ws, hipStream_t s) {
       (void)hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev);
       double us = rate > 0 ? 1e3 / rate : 0.0;  // rate in kHz
       static const char *nm[16] = {"setup", "accum", "flush", "wait", "final", "release", "horner",
-                                   "step0", "spare", "f.round1", "f.res2", "f.div", "f.row", "h.prod", "h.res", "h.round"};
+                                   "step0", "spare", "f.round1", "f.res2", "f.div", "f.row", "h.prod", "h.setup", "h.round"};
       fprintf(stderr, "mpts phases (us):");
       for (int w2 = 0; w2 < 2; ++w2) {
         fprintf(stderr, w2 ? "\n  wg1:" : "\n  leader:");

@@ -461,13 +461,19 @@ __device__ void spin_until_sum(uint32_t *ctr, uint32_t target, uint32_t *err) {
 
 // Spin until *flag >= target (thread 0 only); gives up after ~2 s, marking
 // the error word so that the host reports it instead of hanging.
-__device__ void spin_until(uint32_t *flag, uint32_t target, uint32_t *err) {
+__device__ void spin_until(uint32_t *flag, uint32_t target, uint32_t *err, bool slow = false) {
   long long polls = 0;
   // device-coherent (sc1) plain loads: they see the other workgroups'
-  // atomics without turning every poll into a write at the coherence point
+  // atomics without turning every poll into a write at the coherence point.
+  // A slow spin (a wait of milliseconds) polls every few microseconds, so
+  // that hundreds of waiting workgroups do not crowd the memory path of the
+  // ones at work.
   const __amdgpu_buffer_rsrc_t rs = dev_rsrc(flag, 4);
   while ((uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, 0, 0, 16) < target) {
-    __builtin_amdgcn_s_sleep(2);
+    if (slow)
+      __builtin_amdgcn_s_sleep(127);
+    else
+      __builtin_amdgcn_s_sleep(2);
     if (spin_abandoned(++polls, err)) {
       atomicOr(err, 4u);
       break;
@@ -1212,6 +1218,7 @@ __device__ __noinline__ void tau_chains(const Inst &I, const Carve &cv, int coun
       frame_setup_single(cv.fs, cv.fd, nc, nd, RS);
     }
     __syncthreads();
+    sub(14);
     lds_products(cv.fs, cv.fd, nc, nd, WB, cv.lf);
     __syncthreads();
     sub(13);
@@ -1310,7 +1317,7 @@ __global__ void __launch_bounds__(WGS) k_run(const Inst *__restrict__ insts,
         if (tid == 0)
           __hip_atomic_fetch_add(I.sync + SY_HDONE, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      if (tid == 0) spin_until(I.sync + SY_HDONE, (uint32_t)(3 * (step + 1)), err);
+      if (tid == 0) spin_until(I.sync + SY_HDONE, (uint32_t)(3 * (step + 1)), err, rank >= 3);
       __syncthreads();
       prof_mark(I, cv, PH_HORNER);
     } else if (leader) {

@@ -708,10 +708,12 @@ __device__ void frames_accumulate(const FrameSrc *fs_, const FrameD *fd_, int nf
 
 // One-term frames f = 0..nf-1 whose two rows are in LDS (the Horner
 // products), computed by the whole workgroup into lf[f * WB + c].  The
-// tiles of each anti-diagonal (which share their 16 columns) are cut into
-// runs of up to DRUN tiles; a thread sums a run in registers and adds it
-// into LDS once, so few atomics meet on one column.
+// tiles of each anti-diagonal (which share their 16 columns) are dealt to
+// CPD runs of up to DRUN tiles (every CPD-th tile); a thread sums a run in
+// registers and adds it into LDS once, so few atomics meet on one column.
 constexpr int DRUN = 4;
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) v4i l_v4i;
 
 __device__ void lds_products(const FrameSrc *fs, const FrameD *fd, int nf, int nd, int WB,
                              long long *lf) {
@@ -728,19 +730,20 @@ __device__ void lds_products(const FrameSrc *fs, const FrameD *fd, int nf, int n
       const int d = sl / CPD, c = sl - d * CPD;
       const int mlo = d - MT + 1 > 0 ? d - MT + 1 : 0;
       const int mhi = d < MT - 1 ? d : MT - 1;
-      const int m0 = mlo + c * DRUN;
-      if (m0 > mhi) continue;
-      const int m1 = m0 + DRUN - 1 < mhi ? m0 + DRUN - 1 : mhi;
+      // run c takes the tiles mlo + c, mlo + c + CPD, ... of its diagonal:
+      // the lanes of one diagonal read neighbouring tiles (different LDS
+      // banks), not tiles DRUN apart (the same bank)
+      if (mlo + c > mhi) continue;
       long long acc[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[r] = 0;
-      for (int mt = m0; mt <= m1; ++mt) {
+      for (int mt = mlo + c; mt <= mhi; mt += CPD) {
         const int nt = d - mt;
-        int32_t uu[TQ], vv[TQ];
-#pragma unroll
-        for (int r = 0; r < TQ; ++r) uu[r] = U[mt * TQ + r];
-#pragma unroll
-        for (int r = 0; r < TQ; ++r) vv[r] = V[nt * TQ + r];
+        // 16-byte LDS reads: the rows' digits start 16-byte aligned
+        const l_v4i *u4 = (const l_v4i *)(U + mt * TQ), *v4 = (const l_v4i *)(V + nt * TQ);
+        const v4i ua = u4[0], ub = u4[1], va = v4[0], vb = v4[1];
+        const int32_t uu[TQ] = {ua.x, ua.y, ua.z, ua.w, ub.x, ub.y, ub.z, ub.w};
+        const int32_t vv[TQ] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
         tile_fma(acc, uu, vv);
       }
       acc_flush(acc, lf + (size_t)f * WB + d * TQ);
