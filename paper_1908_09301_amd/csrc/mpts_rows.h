@@ -706,38 +706,54 @@ __device__ void frames_accumulate(const FrameSrc *fs_, const FrameD *fd_, int nf
                            wall_clock64() - tp1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// One-term frames f = 0..nf-1 whose two rows are in LDS (the Horner
-// products), computed by the whole workgroup into lf[f * WB + c].  The
-// tiles of each anti-diagonal (which share their 16 columns) are dealt to
-// CPD runs of up to DRUN tiles (every CPD-th tile); a thread sums a run in
-// registers and adds it into LDS once, so few atomics meet on one column.
-constexpr int DRUN = 4;
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) v4i l_v4i;
 
+// Sum over each aligned group of 8 lanes, in the group's last lane (row
+// shifts by 1, 2 and 4 lanes: an inclusive scan over 8 lanes).  Every lane
+// of the wavefront must be active.
+__device__ __forceinline__ uint32_t dpp_sum8(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true);
+  return x;
+}
+template <int CTRL>
+__device__ __forceinline__ long long dpp_shr_add64(long long v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, 0xf, 0xf, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(
+      0, (int)(uint32_t)((unsigned long long)v >> 32), CTRL, 0xf, 0xf, true);
+  return v + (long long)(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ long long dpp_sum8_64(long long v) {
+  return dpp_shr_add64<0x114>(dpp_shr_add64<0x112>(dpp_shr_add64<0x111>(v)));
+}
+
+// One-term frames f = 0..nf-1 whose two rows are in LDS (the Horner and
+// adjoint power chains), computed by the whole workgroup into
+// lf[f * WB + c]: each anti-diagonal of tiles goes to an aligned
+// group of 8 lanes, lane c taking the tiles c, c + 8, ... of it; the 8 run
+// sums are added across the group in registers and one lane adds them into
+// LDS, so no two lanes of a wavefront add into the same column at once.
 __device__ void lds_products(const FrameSrc *fs, const FrameD *fd, int nf, int nd, int WB,
                              long long *lf) {
   const int tid = threadIdx.x;
   const int MT = (nd + TQ - 1) / TQ;
   const int ND = 2 * MT - 1;                 // anti-diagonals
-  const int CPD = (MT + DRUN - 1) / DRUN;    // run slots per diagonal
-  const int slots = ND * CPD;
+  const int slots = ND * 8;
   for (int f = 0; f < nf; ++f) {
     if (!fd[f].nz) continue;
     const l_i32 *U = (const l_i32 *)fs[f].p[0].U + HDR + RPAD;
     const l_i32 *V = (const l_i32 *)fs[f].p[0].V + HDR + RPAD;
-    for (int sl = tid; sl < slots; sl += WGS) {
-      const int d = sl / CPD, c = sl - d * CPD;
+    for (int sl0 = 0; sl0 < slots; sl0 += WGS) {
+      const int sl = sl0 + tid;
+      const int d = sl >> 3, c = sl & 7;
       const int mlo = d - MT + 1 > 0 ? d - MT + 1 : 0;
-      const int mhi = d < MT - 1 ? d : MT - 1;
-      // run c takes the tiles mlo + c, mlo + c + CPD, ... of its diagonal:
-      // the lanes of one diagonal read neighbouring tiles (different LDS
-      // banks), not tiles DRUN apart (the same bank)
-      if (mlo + c > mhi) continue;
+      const int mhi = d < ND ? (d < MT - 1 ? d : MT - 1) : -1;
       long long acc[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[r] = 0;
-      for (int mt = mlo + c; mt <= mhi; mt += CPD) {
+      for (int mt = mlo + c; mt <= mhi; mt += 8) {
         const int nt = d - mt;
         // 16-byte LDS reads: the rows' digits start 16-byte aligned
         const l_v4i *u4 = (const l_v4i *)(U + mt * TQ), *v4 = (const l_v4i *)(V + nt * TQ);
@@ -746,7 +762,22 @@ __device__ void lds_products(const FrameSrc *fs, const FrameD *fd, int nf, int n
         const int32_t vv[TQ] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
         tile_fma(acc, uu, vv);
       }
-      acc_flush(acc, lf + (size_t)f * WB + d * TQ);
+      tile_normalize(acc);  // columns 0..14 in [0, 2^28): their 8-lane sums fit 32 bits
+      uint32_t s32[15];
+#pragma unroll
+      for (int r = 0; r < 15; ++r) s32[r] = dpp_sum8((uint32_t)acc[r]);
+      const long long top = dpp_sum8_64(acc[15]);
+      if (c == 7 && d < ND) {
+        l_i64 *col = (l_i64 *)lf + (size_t)f * WB + d * TQ;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const long long v = r < 15 ? (long long)s32[r] : top;
+          if (v != 0)
+            __hip_atomic_fetch_add((unsigned long long __attribute__((address_space(3))) *)(col + r),
+                                   (unsigned long long)v, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+      }
     }
   }
 }
