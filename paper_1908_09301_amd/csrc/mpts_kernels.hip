@@ -1212,18 +1212,13 @@ __device__ __noinline__ void tau_chains(const Inst &I, const Carve &cv, int coun
     }
   };
   for (int it = 0; it < count; ++it) {
-    if (tid == 0) {
-      for (int f = 0; f < nc; ++f)
-        cv.fs[f] = mk_frame1(mk_part(PK_ONE, 1, 0, tau_lds, cv.hrow + (size_t)(c0 + f) * RS));
-      frame_setup_single(cv.fs, cv.fd, nc, nd, RS);
-    }
-    __syncthreads();
-    sub(14);
-    lds_products(cv.fs, cv.fd, nc, nd, WB, cv.lf);
+    // the previous iteration's rows are complete (its closing barrier)
+    lds_products(tau_lds, cv.hrow + (size_t)c0 * RS, RS, nc, nd, WB, cv.lf);
     __syncthreads();
     sub(13);
     if (wave < nc) {
       const int c = c0 + wave;  // chain of this wavefront; frame `wave`
+      const FrameD fdw = single_desc(tau_lds, cv.hrow + (size_t)c * RS, nd);
       RowAdd ad;
       int nad = 0;
       if (mode == 0) {  // Horner: i = N-1-it
@@ -1232,11 +1227,11 @@ __device__ __noinline__ void tau_chains(const Inst &I, const Carve &cv, int coun
       }
       int32_t *h = cv.hrow + (size_t)c * RS;
       int32_t *scratch = (int32_t *)(cv.tcols + (size_t)wave * 64 * I.CM);
-      bool ok = sum_to_row<CM>(cv.lf + (size_t)wave * WB, false, &cv.fd[wave], nd, &ad, nad, 0, L,
-                               RS, scratch, h, err);
+      bool ok = sum_to_row<CM>(cv.lf + (size_t)wave * WB, false, &fdw, nd, &ad, nad, 0, L, RS,
+                               scratch, h, err);
       if (!ok && lane == 0) atomicOr(err, 2u);
       if (mode == 1) publish_row(h, q_row(I, c, it + 1), RS, I.G > 1);
-      int ncol = cv.fd[wave].nz ? frame_cols(cv.fd[wave], nd) : 0;
+      int ncol = fdw.nz ? frame_cols(fdw, nd) : 0;
       for (int q = lane; q < ncol; q += 64) ((l_i64 *)cv.lf)[(size_t)wave * WB + q] = 0;
     }
     __syncthreads();

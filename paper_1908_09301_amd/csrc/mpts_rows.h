@@ -407,24 +407,22 @@ __device__ void frame_setup(FrameSrc *fs, FrameD *fd, int nf, int nd, int RS, in
   __syncthreads();
 }
 
-// Frame setup for frames of exactly one term each whose rows are in LDS
-// (the Horner products): thread 0 only, no workgroup reduction.
-__device__ void frame_setup_single(const FrameSrc *fs, FrameD *fd, int nf, int nd, int RS) {
+// Descriptor of the one-term frame U V whose rows are in LDS (the Horner
+// and adjoint power products), from the two row headers.
+__device__ __forceinline__ FrameD single_desc(const int32_t *U_, const int32_t *V_, int nd) {
+  const l_i32 *U = (const l_i32 *)U_, *V = (const l_i32 *)V_;
   const int MT = (nd + TQ - 1) / TQ;
-  for (int f = 0; f < nf; ++f) {
-    FrameD d;
-    const l_i32 *U = (const l_i32 *)fs[f].p[0].U, *V = (const l_i32 *)fs[f].p[0].V;
-    const int e = (U[1] != 0 && V[1] != 0) ? U[0] + V[0] : HZ;
-    d.n = 1;
-    d.nz = e != HZ ? 1 : 0;
-    d.base = d.nz ? e : 0;
-    d.S = 0;
-    d.NT = MT;
-    d.mt0 = 0;
-    d.MTf = MT;
-    d.nt0 = 0;
-    fd[f] = d;
-  }
+  FrameD d;
+  const int e = (U[1] != 0 && V[1] != 0) ? U[0] + V[0] : HZ;
+  d.n = 1;
+  d.nz = e != HZ ? 1 : 0;
+  d.base = d.nz ? e : 0;
+  d.S = 0;
+  d.NT = MT;
+  d.mt0 = 0;
+  d.MTf = MT;
+  d.nt0 = 0;
+  return d;
 }
 
 // Columns spanned by frame f's tiles: [0, (MT + NT) * 8 + 8).
@@ -729,22 +727,23 @@ __device__ __forceinline__ long long dpp_sum8_64(long long v) {
   return dpp_shr_add64<0x114>(dpp_shr_add64<0x112>(dpp_shr_add64<0x111>(v)));
 }
 
-// One-term frames f = 0..nf-1 whose two rows are in LDS (the Horner and
-// adjoint power chains), computed by the whole workgroup into
-// lf[f * WB + c]: each anti-diagonal of tiles goes to an aligned
+// One-term frames f = 0..nf-1, U times the row V0 + f vstride, all in LDS
+// (the Horner and adjoint power chains), computed by the whole workgroup
+// into lf[f * WB + c]: each anti-diagonal of tiles goes to an aligned
 // group of 8 lanes, lane c taking the tiles c, c + 8, ... of it; the 8 run
 // sums are added across the group in registers and one lane adds them into
 // LDS, so no two lanes of a wavefront add into the same column at once.
-__device__ void lds_products(const FrameSrc *fs, const FrameD *fd, int nf, int nd, int WB,
-                             long long *lf) {
+__device__ void lds_products(const int32_t *U_, const int32_t *V0, int vstride, int nf, int nd,
+                             int WB, long long *lf) {
   const int tid = threadIdx.x;
   const int MT = (nd + TQ - 1) / TQ;
   const int ND = 2 * MT - 1;                 // anti-diagonals
   const int slots = ND * 8;
   for (int f = 0; f < nf; ++f) {
-    if (!fd[f].nz) continue;
-    const l_i32 *U = (const l_i32 *)fs[f].p[0].U + HDR + RPAD;
-    const l_i32 *V = (const l_i32 *)fs[f].p[0].V + HDR + RPAD;
+    const l_i32 *Uh = (const l_i32 *)U_, *Vh = (const l_i32 *)(V0 + (size_t)f * vstride);
+    if (Uh[1] == 0 || Vh[1] == 0) continue;  // a zero row: no products
+    const l_i32 *U = Uh + HDR + RPAD;
+    const l_i32 *V = Vh + HDR + RPAD;
     for (int sl0 = 0; sl0 < slots; sl0 += WGS) {
       const int sl = sl0 + tid;
       const int d = sl >> 3, c = sl & 7;
