@@ -1211,18 +1211,34 @@ __device__ __noinline__ void tau_chains(const Inst &I, const Carve &cv, int coun
       tq = t;
     }
   };
+  // Horner addends c_i (i = N-1-it) staged in LDS, two buffers of nc rows
+  // in the task-row area (free while the chains run): wavefront 3, idle
+  // here, loads iteration it+1's rows while iteration it runs
+  int32_t *abuf = cv.trow;
+  auto stage = [&](int it_, int t0, int tstep) {
+    int32_t *dst = abuf + (size_t)(it_ & 1) * nc * RS;
+    for (int f = 0; f < nc; ++f) {
+      const g_i32 *src = (const g_i32 *)row_ptr(I, c0 + f, N - 1 - it_);
+      for (int w = t0; w < RS; w += tstep) ((l_i32 *)dst)[(size_t)f * RS + w] = src[w];
+    }
+  };
+  if (mode == 0 && count > 0) {
+    stage(0, tid, WGS);
+    __syncthreads();
+  }
   for (int it = 0; it < count; ++it) {
     // the previous iteration's rows are complete (its closing barrier)
     lds_products(tau_lds, cv.hrow + (size_t)c0 * RS, RS, nc, nd, WB, cv.lf);
     __syncthreads();
     sub(13);
+    if (mode == 0 && wave == 3 && it + 1 < count) stage(it + 1, lane, 64);
     if (wave < nc) {
       const int c = c0 + wave;  // chain of this wavefront; frame `wave`
       const FrameD fdw = single_desc(tau_lds, cv.hrow + (size_t)c * RS, nd);
       RowAdd ad;
       int nad = 0;
       if (mode == 0) {  // Horner: i = N-1-it
-        ad = RowAdd{row_ptr(I, c, N - 1 - it), 1, 0};
+        ad = RowAdd{abuf + (size_t)((it & 1) * nc + wave) * RS, 1, 1};
         nad = 1;
       }
       int32_t *h = cv.hrow + (size_t)c * RS;
