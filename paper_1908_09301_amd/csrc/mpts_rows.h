@@ -540,7 +540,8 @@ __device__ __forceinline__ void part_tile_terms(long long (&acc)[16], const Fram
 // registers while it stays on one anti-diagonal and adds them into LDS
 // when it leaves it.  Returns through span[2f], span[2f+1] the column range
 // this workgroup touched in frame f (empty: lo >= hi).
-__device__ void frames_accumulate(const FrameSrc *fs_, const FrameD *fd_, int nf, int nd, int RS,
+__device__ __forceinline__ void frames_accumulate(const FrameSrc *fs_, const FrameD *fd_, int nf,
+                                                  int nd, int RS,
                                   int WB, long long *lf, int rank, int G, int *span_,
                                   bool skip0 = false, unsigned long long *tprof = nullptr,
                                   unsigned long long *tmax = nullptr) {
