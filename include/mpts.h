@@ -49,9 +49,12 @@ extern "C" {
 #define MPTS_EARCH (-5)        /* the current device is not gfx950 */
 #define MPTS_EUNSUPPORTED (-6) /* size beyond the compiled limits */
 
-/* Largest exponent difference (in bits) between the terms of one exact
- * sum that the device accumulators hold; beyond it a call fails with
- * MPTS_ERANGE instead of returning an inexact result. */
+/* Exponent difference (in bits) between the terms of one exact sum that
+ * the device accumulators always hold: every sum whose terms lie within
+ * this many bits of each other is exact on every schedule.  A term further
+ * than this from the first term of its sum makes the call fail with
+ * MPTS_ERANGE (some schedules still hold a somewhat wider spread exactly);
+ * a result is never inexact. */
 #define MPTS_MAX_SPREAD_BITS 448
 
 /* flags for mpts_integrate / mpts_integrate_batch */
