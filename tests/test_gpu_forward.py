@@ -50,9 +50,13 @@ def test_z_axis_zero_terms(gpu_lib):
     assert got[0] == (0, 0, 0) and got[1] == (0, 0, 0)
 
 
-@pytest.mark.parametrize("wgs", [1, 2, 7, 0])
+@pytest.mark.parametrize("wgs", [1, 2, 3, 7, 16, 24, 256, 0])
 def test_schedule_does_not_change_bits(gpu_lib, wgs):
-    """Any number of workgroups per trajectory gives the same bits."""
+    """Any number of workgroups per trajectory gives the same bits: one
+    workgroup (every frame in LDS), a leader with one follower, Horner
+    chains on three workgroups, odd counts, the split into eight term
+    groups at its smallest (16, 24) and with every CU (256), and the
+    automatic choice (0)."""
     say("schedule", wgs)
     ctx = lz.make_context(L=12, N=40)
     x0 = lz.state_from_strings(ctx, BENCH_X0)
