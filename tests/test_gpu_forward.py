@@ -80,6 +80,21 @@ def test_k100_n40_full_run_with_checkpoints(gpu_lib):
         assert states[n] == [T(v) for v in ref_states[n]], n
 
 
+def test_k100_n40_matches_stored_states(gpu_lib):
+    """The K=100, N=40 trajectory against the stored oracle states of
+    tests/golden (steps 0, 1, 2, 10, 50, 100), bit for bit."""
+    from test_golden import load_states
+    say("k100 n40 stored states")
+    stored = load_states()
+    ctx = lz.make_context(K_digits=100, N=40)
+    x0 = lz.state_from_strings(ctx, BENCH_X0)
+    last = max(n for n, _ in stored)
+    p = gpu_lib.Lorenz(K=100, N=40)
+    _, states = p.integrate([T(v) for v in x0], last, checkpoints=True)
+    for (n, c), v in stored.items():
+        assert tuple(states[n]["xyz".index(c)]) == v, (n, c)
+
+
 def test_k2000_n600_transition(gpu_lib):
     """One step at K=2000 digits (208 limbs), N=600 from the seeded initial
     state, against the oracle."""
