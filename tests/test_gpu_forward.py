@@ -40,11 +40,17 @@ def test_coefficients_match_oracle(gpu_lib, L, N, ic):
             assert T(r) == q, (name, i)
 
 
-def test_z_axis_zero_terms(gpu_lib):
+@pytest.mark.parametrize("wgs", [0, 1, 7, 256])
+def test_z_axis_zero_terms(gpu_lib, wgs):
+    """x0 = y0 = 0: every coefficient of x and y is an exact zero (zero rows
+    in the Cauchy sums and in the single products), on one workgroup and on
+    groups that split the products."""
+    say("z axis", wgs)
     ctx = lz.make_context(L=12, N=40)
     x0 = (ZERO, ZERO, lz.state_from_strings(ctx, ("0", "0", "35.64"))[2])
     ref = lz.integrate(ctx, x0, 20)
     p = gpu_lib.Lorenz(L=12, N=40)
+    p.set_schedule(wgs)
     got = p.integrate([T(v) for v in x0], 20)
     assert [T(v) for v in ref] == got
     assert got[0] == (0, 0, 0) and got[1] == (0, 0, 0)
@@ -106,10 +112,14 @@ def test_k2000_n600_transition(gpu_lib):
     assert p.integrate([T(v) for v in x0], 1) == [T(v) for v in ref]
 
 
-def test_spread_beyond_window_is_reported(gpu_lib):
+@pytest.mark.parametrize("wgs", [0, 1, 7, 256])
+def test_spread_beyond_window_is_reported(gpu_lib, wgs):
     """A sum whose terms differ by far more than the device window: the call
-    fails with MPTS_ERANGE instead of returning an inexact value."""
+    fails with MPTS_ERANGE instead of returning an inexact value, on every
+    schedule."""
+    say("spread", wgs)
     p = gpu_lib.Lorenz(L=4, N=4)
+    p.set_schedule(wgs)
     ctx = lz.make_context(L=4, N=4)
     x0 = lz.state_from_strings(ctx, ("1e-200", "1", "1"))
     with pytest.raises(gpu_lib.MptsError) as ei:
