@@ -708,13 +708,12 @@ __device__ __forceinline__ void frames_accumulate(const FrameSrc *fs_, const Fra
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) v4i l_v4i;
 
-// Sum over each aligned group of 8 lanes, in the group's last lane (row
-// shifts by 1, 2 and 4 lanes: an inclusive scan over 8 lanes).  Every lane
-// of the wavefront must be active.
-__device__ __forceinline__ uint32_t dpp_sum8(uint32_t x) {
+// Sum over each aligned group of 4 lanes, in the group's last lane (row
+// shifts by 1 and 2 lanes: an inclusive scan over 4 lanes).  Every lane of
+// the wavefront must be active.
+__device__ __forceinline__ uint32_t dpp_sum4(uint32_t x) {
   x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true);
   x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true);
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true);
   return x;
 }
 template <int CTRL>
@@ -724,22 +723,23 @@ __device__ __forceinline__ long long dpp_shr_add64(long long v) {
       0, (int)(uint32_t)((unsigned long long)v >> 32), CTRL, 0xf, 0xf, true);
   return v + (long long)(((unsigned long long)hi << 32) | lo);
 }
-__device__ __forceinline__ long long dpp_sum8_64(long long v) {
-  return dpp_shr_add64<0x114>(dpp_shr_add64<0x112>(dpp_shr_add64<0x111>(v)));
+__device__ __forceinline__ long long dpp_sum4_64(long long v) {
+  return dpp_shr_add64<0x112>(dpp_shr_add64<0x111>(v));
 }
 
 // One-term frames f = 0..nf-1, U times the row V0 + f vstride, all in LDS
 // (the Horner and adjoint power chains), computed by the whole workgroup
 // into lf[f * WB + c]: each anti-diagonal of tiles goes to an aligned
-// group of 8 lanes, lane c taking the tiles c, c + 8, ... of it; the 8 run
-// sums are added across the group in registers and one lane adds them into
-// LDS, so no two lanes of a wavefront add into the same column at once.
+// group of 4 lanes, lane c taking the tiles c, c + 4, ... of it (61
+// diagonals at K=2000 fill one pass of the workgroup); the 4 run sums are
+// added across the group in registers and one lane adds them into LDS, so
+// no two lanes of a wavefront add into the same column at once.
 __device__ void lds_products(const int32_t *U_, const int32_t *V0, int vstride, int nf, int nd,
                              int WB, long long *lf) {
   const int tid = threadIdx.x;
   const int MT = (nd + TQ - 1) / TQ;
   const int ND = 2 * MT - 1;                 // anti-diagonals
-  const int slots = ND * 8;
+  const int slots = ND * 4;
   for (int f = 0; f < nf; ++f) {
     const l_i32 *Uh = (const l_i32 *)U_, *Vh = (const l_i32 *)(V0 + (size_t)f * vstride);
     if (Uh[1] == 0 || Vh[1] == 0) continue;  // a zero row: no products
@@ -747,13 +747,13 @@ __device__ void lds_products(const int32_t *U_, const int32_t *V0, int vstride, 
     const l_i32 *V = Vh + HDR + RPAD;
     for (int sl0 = 0; sl0 < slots; sl0 += WGS) {
       const int sl = sl0 + tid;
-      const int d = sl >> 3, c = sl & 7;
+      const int d = sl >> 2, c = sl & 3;
       const int mlo = d - MT + 1 > 0 ? d - MT + 1 : 0;
       const int mhi = d < ND ? (d < MT - 1 ? d : MT - 1) : -1;
       long long acc[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[r] = 0;
-      for (int mt = mlo + c; mt <= mhi; mt += 8) {
+      for (int mt = mlo + c; mt <= mhi; mt += 4) {
         const int nt = d - mt;
         // 16-byte LDS reads: the rows' digits start 16-byte aligned
         const l_v4i *u4 = (const l_v4i *)(U + mt * TQ), *v4 = (const l_v4i *)(V + nt * TQ);
@@ -762,12 +762,12 @@ __device__ void lds_products(const int32_t *U_, const int32_t *V0, int vstride, 
         const int32_t vv[TQ] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
         tile_fma(acc, uu, vv);
       }
-      tile_normalize(acc);  // columns 0..14 in [0, 2^28): their 8-lane sums fit 32 bits
+      tile_normalize(acc);  // columns 0..14 in [0, 2^28): their 4-lane sums fit 32 bits
       uint32_t s32[15];
 #pragma unroll
-      for (int r = 0; r < 15; ++r) s32[r] = dpp_sum8((uint32_t)acc[r]);
-      const long long top = dpp_sum8_64(acc[15]);
-      if (c == 7 && d < ND) {
+      for (int r = 0; r < 15; ++r) s32[r] = dpp_sum4((uint32_t)acc[r]);
+      const long long top = dpp_sum4_64(acc[15]);
+      if (c == 3 && d < ND) {
         l_i64 *col = (l_i64 *)lf + (size_t)f * WB + d * TQ;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
