@@ -28,6 +28,7 @@ arithmetic with one RNE rounding per quantity:
   and each running parameter adjoint is updated with one rounding per step:
       sigmabar <- round(sigmabar + dsigma)   (same for R, bpar).
 """
+from fractions import Fraction
 from typing import List, Tuple
 
 from .bigfloat import (BF, ZERO, div_round, exact, exact_mul, exact_sum,
@@ -84,16 +85,45 @@ def reverse_step(ctx: Context, state, bar):
     return (abar[0], bbar[0], gbar[0]), (dsig, dR, dbp)
 
 
-def grad_sqnorm(ctx: Context, x0, nsteps: int, states=None):
-    """Gradient of ||x(T)||^2, T = nsteps*tau, with respect to
+# Losses of the final state x(T) = (x, y, z) whose gradient the reverse sweep
+# computes, and the seed (the adjoint of x(T)) each one starts from:
+#   "sqnorm": x^2 + y^2 + z^2, seed 2 x(T) (exact: an exponent increment);
+#   "x", "y", "z": one component of x(T), seed the unit vector (exact).
+LOSSES = ("sqnorm", "x", "y", "z")
+
+ONE_BF = BF(1, 1, 0)
+
+
+def loss_seed(loss: str, xT):
+    """The exact adjoint of x(T) for `loss` (three BF values)."""
+    if loss == "sqnorm":
+        return tuple(BF(v.s, v.m, v.e + 1) if v.s else ZERO for v in xT)
+    if loss in ("x", "y", "z"):
+        j = "xyz".index(loss)
+        return tuple(ONE_BF if c == j else ZERO for c in range(3))
+    raise ValueError(f"unknown loss {loss!r}")
+
+
+def loss_value(loss: str, xT) -> float:
+    """The loss of x(T) computed exactly and rounded once to float64."""
+    if loss == "sqnorm":
+        tot = sum((v.frac() ** 2 for v in xT), Fraction(0))
+        return tot.numerator / tot.denominator
+    if loss in ("x", "y", "z"):
+        return to_double(xT["xyz".index(loss)])
+    raise ValueError(f"unknown loss {loss!r}")
+
+
+def grad(ctx: Context, x0, nsteps: int, loss: str = "sqnorm", states=None):
+    """Gradient of a loss of x(T), T = nsteps*tau, with respect to
     (x0, y0, z0, sigma, R, b), by a forward run with per-step checkpoints
-    and a reverse sweep.  Returns (final_state, grads) where grads is a list
-    of 6 BF values; the seed is the exact 2*x(T)."""
+    and a reverse sweep from the loss's exact seed.  Returns (final_state,
+    grads) where grads is a list of 6 BF values."""
     p = ctx.p
     if states is None:
         _, states = integrate(ctx, x0, nsteps, keep_states=True)
     xT = states[nsteps]
-    bar = tuple(BF(v.s, v.m, v.e + 1) if v.s else ZERO for v in xT)
+    bar = loss_seed(loss, xT)
     psig, pR, pb = ZERO, ZERO, ZERO
     for n in range(nsteps - 1, -1, -1):
         bar, (dsig, dR, dbp) = reverse_step(ctx, states[n], bar)
@@ -101,6 +131,11 @@ def grad_sqnorm(ctx: Context, x0, nsteps: int, states=None):
         pR = round_sum([exact(pR), dR], p)
         pb = round_sum([exact(pb), dbp], p)
     return xT, [bar[0], bar[1], bar[2], psig, pR, pb]
+
+
+def grad_sqnorm(ctx: Context, x0, nsteps: int, states=None):
+    """Gradient of ||x(T)||^2 (the seed is the exact 2*x(T))."""
+    return grad(ctx, x0, nsteps, "sqnorm", states)
 
 
 def grad_sqnorm_fp64(ctx: Context, x0, nsteps: int):

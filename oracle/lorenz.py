@@ -88,28 +88,39 @@ def cauchy_terms(u: Sequence[BF], v: Sequence[BF], i: int):
     return [exact_mul(u[i - k], v[k]) for k in range(i + 1)]
 
 
+def next_coefficients(ctx: Context, a: Sequence[BF], b: Sequence[BF],
+                      g: Sequence[BF], i: int):
+    """One index transition of the recursion (equation (3)): from the
+    coefficients alpha_0..alpha_i, beta_0..beta_i, gamma_0..gamma_i (the
+    lists may be longer; only indices 0..i are read) to alpha_{i+1},
+    beta_{i+1}, gamma_{i+1}.  Returns (alpha_{i+1}, beta_{i+1}, gamma_{i+1},
+    s1_i, s2_i) with the two rounded Cauchy-product sums."""
+    p = ctx.p
+    s1 = round_sum(cauchy_terms(a, g, i), p)
+    s2 = round_sum(cauchy_terms(a, b, i), p)
+    d = i + 1
+    num_a = exact_sum([neg(exact_mul(ctx.sigma, a[i])), exact_mul(ctx.sigma, b[i])])
+    num_b = exact_sum([exact_mul(ctx.R, a[i]), neg(exact(b[i])), neg(exact(s1))])
+    num_g = exact_sum([exact(s2), neg(exact_mul(ctx.b, g[i]))])
+    return (div_round(num_a, d, p), div_round(num_b, d, p), div_round(num_g, d, p), s1, s2)
+
+
 def coefficients(ctx: Context, state: Tuple[BF, BF, BF]):
     """Taylor coefficients alpha, beta, gamma (lists of N+1 BF) and the
     rounded Cauchy sums s1, s2 (lists of N) for one step from `state`
     (equation (3); the i=0 case gives the first-coefficient formulas)."""
-    p = ctx.p
     a: List[BF] = [state[0]]
     b: List[BF] = [state[1]]
     g: List[BF] = [state[2]]
     s1s: List[BF] = []
     s2s: List[BF] = []
     for i in range(ctx.N):
-        s1 = round_sum(cauchy_terms(a, g, i), p)
-        s2 = round_sum(cauchy_terms(a, b, i), p)
+        an, bn, gn, s1, s2 = next_coefficients(ctx, a, b, g, i)
         s1s.append(s1)
         s2s.append(s2)
-        d = i + 1
-        num_a = exact_sum([neg(exact_mul(ctx.sigma, a[i])), exact_mul(ctx.sigma, b[i])])
-        num_b = exact_sum([exact_mul(ctx.R, a[i]), neg(exact(b[i])), neg(exact(s1))])
-        num_g = exact_sum([exact(s2), neg(exact_mul(ctx.b, g[i]))])
-        a.append(div_round(num_a, d, p))
-        b.append(div_round(num_b, d, p))
-        g.append(div_round(num_g, d, p))
+        a.append(an)
+        b.append(bn)
+        g.append(gn)
     return a, b, g, s1s, s2s
 
 
