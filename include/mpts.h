@@ -156,15 +156,53 @@ int mpts_integrate_batch(mpts_ctx *const *ctxs, int32_t count,
                          mpts_bf *x_out, void *workspace, size_t ws_bytes,
                          void *stream, uint32_t flags);
 
-/* Gradient of the loss ||x(T)||^2, T = nsteps*tau, with respect to
- * (x0, y0, z0, sigma, R, b) by a hand-written reverse sweep in the same
- * p-bit arithmetic: per-step states are checkpointed by a forward run and
- * the coefficients are recomputed per step.  grad_out receives 6 doubles
- * (each the RNE of the p-bit result); grad_bf (may be NULL) receives the 6
- * p-bit values; x_out (may be NULL) the final state. */
-int mpts_grad(mpts_ctx *ctx, const mpts_bf x0[3], int64_t nsteps,
-              double grad_out[6], mpts_bf *grad_bf, mpts_bf x_out[3],
+/* Losses of the final state x(T) = (x, y, z), T = nsteps*tau, for the
+ * gradient calls.  Each seeds the reverse sweep with its exact adjoint of
+ * x(T): MPTS_LOSS_SQNORM is x^2 + y^2 + z^2 (seed 2 x(T)); MPTS_LOSS_X,
+ * _Y, _Z are one component of x(T) (seed the unit vector), so the three
+ * give the rows of the Jacobian of x(T) with respect to the inputs. */
+#define MPTS_LOSS_SQNORM 0
+#define MPTS_LOSS_X 1
+#define MPTS_LOSS_Y 2
+#define MPTS_LOSS_Z 3
+
+/* Gradient of a loss of x(T) (MPTS_LOSS_*) with respect to (x0, y0, z0,
+ * sigma, R, b) by a hand-written reverse sweep of equations (2)-(3) in the
+ * same p-bit arithmetic: per-step states are checkpointed by a forward run
+ * and the coefficients are recomputed per step; the derivative with respect
+ * to b is taken at the p-bit b.  grad_out receives 6 doubles (each the RNE of
+ * the p-bit result); loss_out (may be NULL) the loss of the p-bit final state,
+ * computed exactly and rounded once to double; grad_bf (may be NULL) the 6
+ * p-bit values; x_out (may be NULL) the final state.  The workspace size is
+ * mpts_workspace_bytes(ctx, nsteps, MPTS_CHECKPOINTS).  Synchronises
+ * `stream`.  Errors: MPTS_EINVAL (unknown loss, null pointer), MPTS_ENOSPC,
+ * MPTS_ERANGE, MPTS_EUNSUPPORTED (the reverse kernel does not fit one
+ * compute unit at this L, N), MPTS_EHIP. */
+int mpts_grad(mpts_ctx *ctx, const mpts_bf x0[3], int64_t nsteps, int32_t loss,
+              double grad_out[6], double *loss_out, mpts_bf *grad_bf, mpts_bf x_out[3],
               void *workspace, size_t ws_bytes, void *stream);
+
+/* Gradients of `count` trajectories in one forward launch and one reverse
+ * launch: trajectory t has context ctxs[t] (its own K, N), initial state
+ * x0[3t..3t+2] and nsteps[t] steps; grad_out receives 6 doubles per
+ * trajectory (grad_out[6t..6t+5], ordered as in mpts_grad), loss_out (may
+ * be NULL) `count` losses, x_out (may be NULL) 3*count final states.  All
+ * trajectories use the same loss.  Each result equals what mpts_grad
+ * returns for that trajectory alone (bit for bit).  The device workspace
+ * size comes from mpts_grad_batch_workspace_bytes.  Synchronises `stream`.
+ * Errors as mpts_grad; MPTS_EUNSUPPORTED also when count exceeds the
+ * workgroups resident at once. */
+int mpts_grad_batch_workspace_bytes(mpts_ctx *const *ctxs, int32_t count,
+                                    const int64_t *nsteps, size_t *bytes);
+int mpts_grad_batch(mpts_ctx *const *ctxs, int32_t count, const mpts_bf *x0,
+                    const int64_t *nsteps, int32_t loss, double *grad_out,
+                    double *loss_out, mpts_bf *x_out, void *workspace,
+                    size_t ws_bytes, void *stream);
+
+/* Destroys every cached instantiated batch graph (mpts_destroy already
+ * evicts the graphs of the context it frees).  For an orderly shutdown
+ * before the HIP runtime is torn down; later batch calls re-capture. */
+int mpts_release_caches(void);
 
 const char *mpts_strerror(int status);
 /* Text of the last error recorded on this context ("" if none). */

@@ -65,7 +65,7 @@ struct Inst {
   int L, N, nd, RS, WB, CM;  // limbs, order, digits/row, row stride, frame width, chunk max
   int G, wg0;                // workgroups of the group and the first one
   int mode;
-  int pad0;
+  int loss;           // adjoint seed: 0 = 2 x(T) (squared norm), 1..3 = unit vector e_x, e_y, e_z
   long long nsteps;
   int32_t *rows;      // [3][N+1][RS]
   int32_t *consts;    // [NCONST][RS]

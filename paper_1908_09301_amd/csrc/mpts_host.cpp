@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <map>
+#include <mutex>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -278,11 +280,62 @@ double nv_to_double(const int32_t *nv, int L) {
   return s > 0 ? v : -v;
 }
 
+void add_in(Big &a, const Big &b) {  // a += b
+  if (a.size() < b.size()) a.resize(b.size(), 0u);
+  uint64_t c = 0;
+  for (size_t i = 0; i < a.size(); ++i) {
+    uint64_t t = (uint64_t)a[i] + (i < b.size() ? b[i] : 0u) + c;
+    a[i] = (uint32_t)t;
+    c = t >> 32;
+  }
+  if (c) a.push_back((uint32_t)c);
+}
+
+// x^2 + y^2 + z^2 of a normalised state [sign, E, M[L]] x 3, computed
+// exactly and rounded once to the nearest double.
+double exact_sqnorm(const int32_t *st, int L) {
+  std::vector<Big> sq;
+  std::vector<long long> ex;
+  for (int c = 0; c < 3; ++c) {
+    const int32_t *nv = st + (size_t)c * (L + 2);
+    if (nv[0] == 0) continue;
+    Big m((const uint32_t *)(nv + 2), (const uint32_t *)(nv + 2) + L);
+    trim(m);
+    sq.push_back(mul(m, m));
+    ex.push_back(2LL * nv[1]);
+  }
+  if (sq.empty()) return 0.0;
+  const long long emin = *std::min_element(ex.begin(), ex.end());
+  Big S;
+  for (size_t k = 0; k < sq.size(); ++k) add_in(S, shl(sq[k], ex[k] - emin));
+  trim(S);
+  // the exact sum as a normalised value of Lb limbs (no rounding), then RNE
+  const long long bits = bitlen(S);
+  const int Lb = (int)((bits + 31) / 32);
+  const long long up = 32LL * Lb - bits;
+  Big M = shl(S, up);
+  M.resize((size_t)Lb, 0u);
+  std::vector<int32_t> nv((size_t)Lb + 2);
+  nv[0] = 1;
+  const long long E = emin - up;
+  if (E < INT32_MIN || E > INT32_MAX) return E > 0 ? INFINITY : 0.0;
+  nv[1] = (int32_t)E;
+  for (int j = 0; j < Lb; ++j) nv[2 + j] = (int32_t)M[j];
+  return nv_to_double(nv.data(), Lb);
+}
+
+// The loss of a final state (MPTS_LOSS_*), rounded once to double.
+double loss_of_state(const int32_t *st, int L, int loss) {
+  if (loss == MPTS_LOSS_SQNORM) return exact_sqnorm(st, L);
+  return nv_to_double(st + (size_t)(loss - 1) * (L + 2), L);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 struct mpts_ctx {
   int L, N, nd, RS, WB, CM;
+  uint64_t gen = 0;          // creation number, never reused (keys the graph cache)
   std::vector<int32_t> cn;  // NCONST x (L+2) normalised constants
   int wgs = 0;
   int cus = 0;
@@ -406,6 +459,8 @@ int make_ctx(const char *sigma, const char *R, const char *b, int L, int N, cons
       !parse_number(tau, qt))
     return MPTS_EINVAL;
   mpts_ctx *c = new mpts_ctx();
+  static std::atomic<uint64_t> next_gen{1};
+  c->gen = next_gen.fetch_add(1);
   c->L = L;
   c->N = N;
   c->nd = digits_per_row(L);
@@ -471,7 +526,7 @@ int default_groups(const mpts_ctx *c) {
 
 int run_single(mpts_ctx *c, int mode, long long nsteps, const void *x0_dev, void *xout_dev,
                void *ckpt_dev, void *ws, size_t ws_bytes, hipStream_t s, bool x0_on_host,
-               const int32_t *x0_host, void *adj_dev = nullptr) {
+               const int32_t *x0_host, void *adj_dev = nullptr, int loss = 0) {
   int dst = check_device(c);
   if (dst != MPTS_OK) return dst;
   const bool adj = mode == MODE_ADJOINT;
@@ -515,6 +570,7 @@ int run_single(mpts_ctx *c, int mode, long long nsteps, const void *x0_dev, void
   I.G = G;
   I.wg0 = 0;
   I.mode = mode;
+  I.loss = loss;
   I.nsteps = nsteps;
   I.rows = (int32_t *)(base + l.rows);
   I.consts = (int32_t *)(base + l.consts);
@@ -657,24 +713,89 @@ int batch_layout(mpts_ctx *const *ctxs, int count, BatchLayout &bl) {
   return MPTS_OK;
 }
 
-// Measured milliseconds per step of one trajectory class at 1, 2, 4, 8
-// workgroups (filled by the autotuner; keyed by L and N).
-std::map<std::pair<int, int>, std::vector<double>> g_tune;
+// The graph and tuning caches are shared by every context of the process;
+// g_cache_mu serialises their use (the kernels they launch are still
+// ordered only by the caller's streams).
+std::mutex g_cache_mu;
 
-double step_ms(const mpts_ctx *c, int G) {
-  auto it = g_tune.find({c->L, c->N});
+// Measured milliseconds per step of one trajectory class at each of the
+// group sizes kTuneG (filled by the autotuner), keyed by the device
+// architecture and the class's (L, N).  With MPTS_TUNE_CACHE set to a file
+// path the table is read from that file once and every new entry appended
+// to it ("arch L N ms..." per line), so later processes skip the probes.
+constexpr int kTuneN = 6;
+constexpr int kTuneG[kTuneN] = {1, 2, 4, 8, 16, 32};
+struct TuneKey {
+  std::string arch;
+  int L, N;
+  bool operator<(const TuneKey &o) const {
+    if (arch != o.arch) return arch < o.arch;
+    if (L != o.L) return L < o.L;
+    return N < o.N;
+  }
+};
+std::map<TuneKey, std::vector<double>> g_tune;
+bool g_tune_loaded = false;
+
+std::string device_arch() {
+  int dev = 0;
+  hipDeviceProp_t pr;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&pr, dev) != hipSuccess)
+    return "unknown";
+  std::string a(pr.gcnArchName);
+  size_t colon = a.find(':');
+  return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+void tune_load() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char *path = getenv("MPTS_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE *f = fopen(path, "r");
+  if (!f) return;
+  char arch[64];
+  int L, N;
+  while (fscanf(f, "%63s %d %d", arch, &L, &N) == 3) {
+    std::vector<double> ms(kTuneN, -1.0);
+    bool ok = true;
+    for (int k = 0; k < kTuneN && ok; ++k) ok = fscanf(f, "%lf", &ms[k]) == 1;
+    if (!ok) break;
+    g_tune[TuneKey{arch, L, N}] = ms;
+  }
+  fclose(f);
+}
+
+void tune_store(const TuneKey &k, const std::vector<double> &ms) {
+  g_tune[k] = ms;
+  const char *path = getenv("MPTS_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE *f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "%s %d %d", k.arch.c_str(), k.L, k.N);
+  for (double v : ms) fprintf(f, " %.6f", v);
+  fprintf(f, "\n");
+  fclose(f);
+}
+
+double step_ms(const mpts_ctx *c, int G, const std::string &arch) {
+  auto it = g_tune.find(TuneKey{arch, c->L, c->N});
   if (it != g_tune.end()) {
-    int k = G == 1 ? 0 : G == 2 ? 1 : G == 4 ? 2 : 3;
-    if (it->second[k] > 0) return it->second[k];
+    // a group size the tuner did not time (it stopped once larger groups
+    // got slower) is not a candidate
+    for (int k = 0; k < kTuneN; ++k)
+      if (kTuneG[k] == G) return it->second[k] > 0 ? it->second[k] : 1e30;
+    return 1e30;
   }
   return model_ms(c, G);
 }
 
-// Time a few steps of one trajectory of context c at each of 1, 2, 4, 8
-// workgroups, in the caller's workspace, and record them in g_tune.
-int autotune_class(mpts_ctx *c, void *ws, size_t ws_bytes, hipStream_t s) {
-  if (g_tune.count({c->L, c->N})) return MPTS_OK;
-  std::vector<double> ms(4, -1.0);
+// Time a few steps of one trajectory of context c at each group size of
+// kTuneG (up to `gmax`), in the caller's workspace, and record them.
+int autotune_class(mpts_ctx *c, void *ws, size_t ws_bytes, hipStream_t s, int gmax,
+                   const std::string &arch) {
+  if (g_tune.count(TuneKey{arch, c->L, c->N})) return MPTS_OK;
+  std::vector<double> ms(kTuneN, -1.0);
   std::vector<int32_t> x((size_t)3 * (c->L + 2), 0);
   // a generic nonzero state: (1, 2, 3)
   for (int k = 0; k < 3; ++k) {
@@ -689,10 +810,10 @@ int autotune_class(mpts_ctx *c, void *ws, size_t ws_bytes, hipStream_t s) {
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return set_err(c, MPTS_EHIP, "event");
-  const int gs[4] = {1, 2, 4, 8};
   int rc = MPTS_OK;
-  for (int k = 0; k < 4 && rc == MPTS_OK; ++k) {
-    c->wgs = gs[k];
+  for (int k = 0; k < kTuneN && rc == MPTS_OK; ++k) {
+    if (kTuneG[k] > gmax) break;
+    c->wgs = kTuneG[k];
     const long long steps = 2;
     rc = run_single(c, MODE_INTEGRATE, 1, nullptr, nullptr, nullptr, ws, ws_bytes, s, true, x.data());
     if (rc) break;
@@ -705,12 +826,14 @@ int autotune_class(mpts_ctx *c, void *ws, size_t ws_bytes, hipStream_t s) {
     float t = 0.f;
     (void)hipEventElapsedTime(&t, e0, e1);
     ms[k] = t / steps;
+    // a larger group that is already slower will not be chosen: stop probing
+    if (k > 0 && ms[k] > ms[k - 1]) break;
   }
   c->wgs = saved;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
-  g_tune[{c->L, c->N}] = ms;
+  tune_store(TuneKey{arch, c->L, c->N}, ms);
   return MPTS_OK;
 }
 
@@ -725,9 +848,15 @@ int plan_batch(mpts_ctx *const *ctxs, int count, const int64_t *nsteps, const Ba
     return set_err(c0, MPTS_EUNSUPPORTED, "kernel does not fit one compute unit");
   const int cap = std::min(c0->cus * per_cu, kMaxWG);
   if (count > cap) return set_err(c0, MPTS_EUNSUPPORTED, "more trajectories than resident workgroups");
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  tune_load();
+  const std::string arch = device_arch();
+  // a trajectory never takes more than an equal share of the resident
+  // workgroups beyond its first (nor more than the largest tuned group)
+  const int gmax = std::max(1, std::min(kTuneG[kTuneN - 1], cap - count + 1));
   if (autotune)
     for (int t = 0; t < count; ++t) {
-      int st = autotune_class(ctxs[t], ws, ws_bytes, s);
+      int st = autotune_class(ctxs[t], ws, ws_bytes, s, gmax, arch);
       if (st) return st;
     }
   G.assign((size_t)count, 1);
@@ -736,30 +865,77 @@ int plan_batch(mpts_ctx *const *ctxs, int count, const int64_t *nsteps, const Ba
     int worst = -1;
     double tw = -1.0;
     for (int t = 0; t < count; ++t) {
-      double tt = nsteps[t] * step_ms(ctxs[t], G[t]);
+      double tt = nsteps[t] * step_ms(ctxs[t], G[t], arch);
       if (tt > tw) {
         tw = tt;
         worst = t;
       }
     }
-    if (worst < 0 || G[worst] >= 8) break;
+    if (worst < 0 || G[worst] >= gmax) break;
     int ng = G[worst] * 2;
     if (used + (ng - G[worst]) > cap) break;
-    if (step_ms(ctxs[worst], ng) >= step_ms(ctxs[worst], G[worst])) break;
+    if (step_ms(ctxs[worst], ng, arch) >= step_ms(ctxs[worst], G[worst], arch)) break;
     used += ng - G[worst];
     G[worst] = ng;
   }
   return MPTS_OK;
 }
 
+// Workspace of a batch of gradients: descriptors, workgroup map, then one
+// region per trajectory laid out like a single checkpointed run.
+struct GradBatchLayout {
+  std::vector<size_t> region;
+  size_t insts = 0, wgmap = 0, total = 0;
+  int CM = 4;
+  size_t lds_fwd = 0, lds_adj = 0;
+};
+
+int grad_batch_layout(mpts_ctx *const *ctxs, int count, const int64_t *nsteps, GradBatchLayout &gl) {
+  gl = GradBatchLayout();
+  size_t o = 0;
+  gl.insts = o;
+  o = al(o + (size_t)count * sizeof(Inst));
+  gl.wgmap = o;
+  o = al(o + (size_t)kMaxWG * 4);
+  int maxnd = 0;
+  for (int t = 0; t < count; ++t) {
+    gl.region.push_back(o);
+    o = al(o + layout(ctxs[t], nsteps[t], true, 1).total);
+    maxnd = std::max(maxnd, ctxs[t]->nd);
+  }
+  gl.total = o;
+  gl.CM = choose_cm(maxnd);
+  if (gl.CM < 0) return MPTS_EUNSUPPORTED;
+  for (int t = 0; t < count; ++t) {
+    mpts_ctx *c = ctxs[t];
+    gl.lds_fwd = std::max(gl.lds_fwd, lds_bytes(c->L, c->N, c->RS, c->WB, gl.CM, false));
+    gl.lds_adj = std::max(gl.lds_adj, lds_bytes(c->L, c->N, c->RS, c->WB, gl.CM, true));
+  }
+  return MPTS_OK;
+}
+
+// Cached instantiated graphs of batch launches.  A graph holds the kernel
+// instance (CM), its dynamic LDS size, the workgroup count and the clear
+// nodes of every trajectory's region, all of which follow from the
+// trajectories' (L, N), nsteps and schedule: the key names each trajectory
+// by its context's creation number (never reused, unlike an address) and
+// its sizes, and mpts_destroy evicts every graph that names the context.
 struct GraphKey {
   void *ws = nullptr;
-  std::vector<mpts_ctx *> ctxs;
+  int device = 0;
+  int CM = 0;
+  size_t lds = 0;
+  std::vector<uint64_t> gens;
+  std::vector<int> LN;  // L, N per trajectory
   std::vector<int64_t> nsteps;
   std::vector<int> G;
   bool operator<(const GraphKey &o) const {
     if (ws != o.ws) return ws < o.ws;
-    if (ctxs != o.ctxs) return ctxs < o.ctxs;
+    if (device != o.device) return device < o.device;
+    if (CM != o.CM) return CM < o.CM;
+    if (lds != o.lds) return lds < o.lds;
+    if (gens != o.gens) return gens < o.gens;
+    if (LN != o.LN) return LN < o.LN;
     if (nsteps != o.nsteps) return nsteps < o.nsteps;
     return G < o.G;
   }
@@ -777,6 +953,17 @@ void graph_store(const GraphKey &k, hipGraphExec_t e) {
     g_graphs.clear();
   }
   g_graphs[k] = e;
+}
+
+void graph_evict(uint64_t gen) {
+  for (auto it = g_graphs.begin(); it != g_graphs.end();) {
+    if (std::find(it->first.gens.begin(), it->first.gens.end(), gen) != it->first.gens.end()) {
+      (void)hipGraphExecDestroy(it->second);
+      it = g_graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
 }
 
 }  // namespace
@@ -799,7 +986,21 @@ int mpts_create_limbs(const char *sigma, const char *R, const char *b, int32_t L
   return make_ctx(sigma, R, b, L, N, tau, out);
 }
 
-void mpts_destroy(mpts_ctx *ctx) { delete ctx; }
+void mpts_destroy(mpts_ctx *ctx) {
+  if (!ctx) return;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    graph_evict(ctx->gen);
+  }
+  delete ctx;
+}
+
+int mpts_release_caches(void) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  for (auto &kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
+  g_graphs.clear();
+  return MPTS_OK;
+}
 
 int mpts_limbs(const mpts_ctx *c, int32_t *L, int32_t *p_bits, int32_t *N) {
   if (!c) return MPTS_EINVAL;
@@ -1068,9 +1269,17 @@ int mpts_integrate_batch(mpts_ctx *const *ctxs, int32_t count, const mpts_bf *x0
   if (flags & MPTS_GRAPH) {
     GraphKey key;
     key.ws = ws;
-    key.ctxs.assign(ctxs, ctxs + count);
+    (void)hipGetDevice(&key.device);
+    key.CM = bl.CM;
+    key.lds = bl.lds;
+    for (int t = 0; t < count; ++t) {
+      key.gens.push_back(ctxs[t]->gen);
+      key.LN.push_back(ctxs[t]->L);
+      key.LN.push_back(ctxs[t]->N);
+    }
     key.nsteps.assign(nsteps, nsteps + count);
     key.G = G;
+    std::lock_guard<std::mutex> lk(g_cache_mu);
     hipGraphExec_t exec = graph_lookup(key);
     if (!exec) {
       // capture on a private stream (the caller's may be the legacy default
@@ -1127,9 +1336,11 @@ int mpts_integrate_batch(mpts_ctx *const *ctxs, int32_t count, const mpts_bf *x0
   return MPTS_OK;
 }
 
-int mpts_grad(mpts_ctx *c, const mpts_bf x0[3], int64_t nsteps, double grad_out[6],
-              mpts_bf *grad_bf, mpts_bf x_out[3], void *ws, size_t ws_bytes, void *stream) {
+int mpts_grad(mpts_ctx *c, const mpts_bf x0[3], int64_t nsteps, int32_t loss,
+              double grad_out[6], double *loss_out, mpts_bf *grad_bf, mpts_bf x_out[3],
+              void *ws, size_t ws_bytes, void *stream) {
   if (!c || !x0 || !grad_out || !ws || nsteps < 0) return MPTS_EINVAL;
+  if (loss < MPTS_LOSS_SQNORM || loss > MPTS_LOSS_Z) return set_err(c, MPTS_EINVAL, "unknown loss");
   hipStream_t s = (hipStream_t)stream;
   std::vector<int32_t> packed((size_t)3 * (c->L + 2));
   int st = mpts_pack_state(c, x0, packed.data());
@@ -1145,7 +1356,7 @@ int mpts_grad(mpts_ctx *c, const mpts_bf x0[3], int64_t nsteps, double grad_out[
   if (st) return st;
   // reverse sweep (the state buffer is not read in this mode)
   st = run_single(c, MODE_ADJOINT, nsteps, nullptr, nullptr, base + l.ckpt, ws, ws_bytes, s, true,
-                  packed.data(), base + l.adj);
+                  packed.data(), base + l.adj, loss);
   if (st) return st;
   const size_t nvw = (size_t)c->L + 2;
   std::vector<int32_t> bars(6 * nvw), fin(3 * nvw);
@@ -1165,7 +1376,168 @@ int mpts_grad(mpts_ctx *c, const mpts_bf x0[3], int64_t nsteps, double grad_out[
       if (st) return st;
     }
   }
+  if (loss_out) *loss_out = loss_of_state(fin.data(), c->L, loss);
   if (x_out) return mpts_unpack_state(c, fin.data(), x_out);
+  return MPTS_OK;
+}
+
+int mpts_grad_batch_workspace_bytes(mpts_ctx *const *ctxs, int32_t count, const int64_t *nsteps,
+                                    size_t *bytes) {
+  if (!ctxs || count < 1 || !nsteps || !bytes) return MPTS_EINVAL;
+  GradBatchLayout gl;
+  int st = grad_batch_layout(ctxs, count, nsteps, gl);
+  if (st) return st;
+  *bytes = gl.total;
+  return MPTS_OK;
+}
+
+int mpts_grad_batch(mpts_ctx *const *ctxs, int32_t count, const mpts_bf *x0, const int64_t *nsteps,
+                    int32_t loss, double *grad_out, double *loss_out, mpts_bf *x_out, void *ws,
+                    size_t ws_bytes, void *stream) {
+  if (!ctxs || count < 1 || !x0 || !nsteps || !grad_out || !ws) return MPTS_EINVAL;
+  for (int t = 0; t < count; ++t)
+    if (!ctxs[t] || nsteps[t] < 0) return MPTS_EINVAL;
+  mpts_ctx *c0 = ctxs[0];
+  if (loss < MPTS_LOSS_SQNORM || loss > MPTS_LOSS_Z) return set_err(c0, MPTS_EINVAL, "unknown loss");
+  hipStream_t s = (hipStream_t)stream;
+  for (int t = 0; t < count; ++t) {
+    int st = check_device(ctxs[t]);
+    if (st) return st;
+  }
+  GradBatchLayout gl;
+  int st = grad_batch_layout(ctxs, count, nsteps, gl);
+  if (st) return set_err(c0, st, "batch layout");
+  if (ws_bytes < gl.total) return set_err(c0, MPTS_ENOSPC, "workspace too small");
+  // residency of both kernels at the batch's chunk size and LDS sizes
+  int pf = 0, pa = 0;
+  if (max_coresident(gl.CM, gl.lds_fwd, &pf, false) != 0 || pf < 1)
+    return set_err(c0, MPTS_EUNSUPPORTED, "kernel does not fit one compute unit");
+  if (max_coresident(gl.CM, gl.lds_adj, &pa, true) != 0 || pa < 1)
+    return set_err(c0, MPTS_EUNSUPPORTED, "adjoint kernel does not fit one compute unit");
+  const int cap = std::min(c0->cus * std::min(pf, pa), kMaxWG);
+  if (count > cap) return set_err(c0, MPTS_EUNSUPPORTED, "more trajectories than resident workgroups");
+  // workgroups per trajectory: each trajectory's own single-run choice,
+  // within an equal share of the resident workgroups
+  int share = 1;
+  while (share * 2 * count <= cap) share *= 2;
+  std::vector<int> G((size_t)count);
+  int total = 0;
+  for (int t = 0; t < count; ++t) {
+    G[t] = std::max(1, std::min(ctxs[t]->wgs > 0 ? ctxs[t]->wgs : default_groups(ctxs[t]), share));
+    total += G[t];
+  }
+  char *base = (char *)ws;
+  std::vector<Inst> insts((size_t)count);
+  std::vector<int> wgmap((size_t)total);
+  int wg = 0;
+  hipError_t e;
+  // packed initial states (alive until the stream is synchronised below)
+  std::vector<std::vector<int32_t>> packs((size_t)count);
+  for (int t = 0; t < count; ++t) {
+    mpts_ctx *c = ctxs[t];
+    char *rb = base + gl.region[t];
+    Layout l = layout(c, nsteps[t], true, 1);
+    std::vector<int32_t> &packed = packs[t];
+    packed.resize((size_t)3 * (c->L + 2));
+    st = mpts_pack_state(c, x0 + 3 * t, packed.data());
+    if (st) return set_err(c0, st, "bad initial state");
+    Inst &I = insts[t];
+    memset(&I, 0, sizeof(I));
+    I.L = c->L;
+    I.N = c->N;
+    I.nd = c->nd;
+    I.RS = c->RS;
+    I.WB = c->WB;
+    I.CM = gl.CM;
+    I.G = G[t];
+    I.wg0 = wg;
+    I.mode = MODE_INTEGRATE;
+    I.loss = loss;
+    I.nsteps = nsteps[t];
+    I.rows = (int32_t *)(rb + l.rows);
+    I.consts = (int32_t *)(rb + l.consts);
+    I.cnorm = (int32_t *)(rb + l.cnorm);
+    I.state = (int32_t *)(rb + l.state);
+    I.ckpt = (int32_t *)(rb + l.ckpt);
+    I.gframes = (long long *)(rb + l.gframes);
+    I.sync = (uint32_t *)(rb + l.sync);
+    I.adj = (int32_t *)(rb + l.adj);
+    for (int j = 0; j < G[t]; ++j) wgmap[wg + j] = t;
+    wg += G[t];
+    e = hipMemcpyAsync(rb + l.cnorm, c->cn.data(), c->cn.size() * 4, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_err(c0, e, "copy constants");
+    e = hipMemcpyAsync(rb + l.state, packed.data(), packed.size() * 4, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_err(c0, e, "copy state");
+  }
+  e = hipMemcpyAsync(base + gl.wgmap, wgmap.data(), wgmap.size() * 4, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_err(c0, e, "copy map");
+  auto clear_regions = [&]() -> hipError_t {
+    for (int t = 0; t < count; ++t) {
+      Layout l = layout(ctxs[t], nsteps[t], true, 1);
+      char *rb = base + gl.region[t];
+      hipError_t e2 = launch_clear(rb + l.sync, SY_WORDS * 4, s);
+      if (e2 != hipSuccess) return e2;
+      e2 = launch_clear(rb + l.gframes, (size_t)2 * NFR * ctxs[t]->WB * 8, s);
+      if (e2 != hipSuccess) return e2;
+    }
+    return hipSuccess;
+  };
+  // 1. forward runs with per-step checkpoints
+  e = hipMemcpyAsync(base + gl.insts, insts.data(), insts.size() * sizeof(Inst),
+                     hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = clear_regions();
+  if (e == hipSuccess)
+    e = launch_run((const Inst *)(base + gl.insts), (const int *)(base + gl.wgmap), total, gl.CM,
+                   gl.lds_fwd, s, true);
+  if (e != hipSuccess) return hip_err(c0, e, "forward launch");
+  e = hipStreamSynchronize(s);  // the descriptors are rewritten below
+  if (e != hipSuccess) return hip_err(c0, e, "synchronize");
+  // 2. reverse sweeps
+  for (auto &I : insts) I.mode = MODE_ADJOINT;
+  e = hipMemcpyAsync(base + gl.insts, insts.data(), insts.size() * sizeof(Inst),
+                     hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = clear_regions();
+  if (e == hipSuccess)
+    e = launch_adj((const Inst *)(base + gl.insts), (const int *)(base + gl.wgmap), total, gl.CM,
+                   gl.lds_adj, s);
+  if (e != hipSuccess) return hip_err(c0, e, "adjoint launch");
+  // 3. results: six adjoints, the final state and the status of each
+  std::vector<std::vector<int32_t>> bars((size_t)count), fins((size_t)count);
+  std::vector<uint32_t> errs((size_t)count, 0u);
+  for (int t = 0; t < count; ++t) {
+    mpts_ctx *c = ctxs[t];
+    Layout l = layout(c, nsteps[t], true, 1);
+    char *rb = base + gl.region[t];
+    const size_t nvw = (size_t)c->L + 2;
+    bars[t].resize(6 * nvw);
+    fins[t].resize(3 * nvw);
+    const size_t bar_off =
+        l.adj + ((size_t)6 * c->N * c->RS + (size_t)3 * (c->N + 1) * c->RS) * 4;
+    e = hipMemcpyAsync(bars[t].data(), rb + bar_off, bars[t].size() * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(fins[t].data(), rb + l.ckpt + (size_t)nsteps[t] * 3 * nvw * 4,
+                         fins[t].size() * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&errs[t], rb + l.sync + SY_ERROR * 4, 4, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_err(c0, e, "copy results");
+  }
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_err(c0, e, "synchronize");
+  for (int t = 0; t < count; ++t) {
+    if (errs[t] & 4u) return set_err(c0, MPTS_EHIP, "device synchronisation timed out");
+    if (errs[t] & 8u) return set_err(c0, MPTS_EUNSUPPORTED, "per-term offset table overflow");
+    if (errs[t] & 3u) return set_err(c0, MPTS_ERANGE, "exact sum outside the device window");
+  }
+  for (int t = 0; t < count; ++t) {
+    mpts_ctx *c = ctxs[t];
+    const size_t nvw = (size_t)c->L + 2;
+    for (int j = 0; j < 6; ++j) grad_out[6 * t + j] = nv_to_double(bars[t].data() + j * nvw, c->L);
+    if (loss_out) loss_out[t] = loss_of_state(fins[t].data(), c->L, loss);
+    if (x_out) {
+      st = mpts_unpack_state(c, fins[t].data(), x_out + 3 * t);
+      if (st) return st;
+    }
+  }
   return MPTS_OK;
 }
 

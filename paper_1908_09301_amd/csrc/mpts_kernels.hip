@@ -1391,11 +1391,18 @@ __global__ void __launch_bounds__(WGS) k_adj(const Inst *__restrict__ insts,
   if (leader) {
     for (int c = wave; c < NCONST; c += 4)
       write_row(I.cnorm + (size_t)c * (L + 2), L, nd, RS, I.consts + (size_t)c * RS, rel, lane, 64);
-    // seed: the adjoint of ||x(T)||^2 is 2 x(T) (exact); parameter adjoints 0
+    // seed: the adjoint of ||x(T)||^2 is 2 x(T), that of one component of
+    // x(T) the unit vector (both exact); parameter adjoints 0
     if (wave < 3) {
-      const int32_t *xT = I.ckpt + ((size_t)I.nsteps * 3 + wave) * (L + 2);
       int32_t *b = bar_ptr(I, wave);
-      for (int j = lane; j < L + 2; j += 64) b[j] = (j == 1 && xT[0] != 0) ? xT[1] + 1 : xT[j];
+      if (I.loss == 0) {
+        const int32_t *xT = I.ckpt + ((size_t)I.nsteps * 3 + wave) * (L + 2);
+        for (int j = lane; j < L + 2; j += 64) b[j] = (j == 1 && xT[0] != 0) ? xT[1] + 1 : xT[j];
+      } else {
+        const int32_t *one = I.cnorm + (size_t)C_ONE * (L + 2);
+        const bool unit = wave == I.loss - 1;
+        for (int j = lane; j < L + 2; j += 64) b[j] = unit ? one[j] : 0;
+      }
       int32_t *pb = bar_ptr(I, 3 + wave);
       for (int j = lane; j < L + 2; j += 64) pb[j] = 0;
     }

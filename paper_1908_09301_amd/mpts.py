@@ -6,6 +6,7 @@ from PyTorch tensors and the stream is PyTorch's current stream.  Every step
 of the computation runs in the HIP library; importing this module fails
 loudly when the library is missing.
 """
+import atexit
 import ctypes
 import os
 from typing import List, Optional, Sequence, Tuple
@@ -23,6 +24,11 @@ MPTS_EUNSUPPORTED = -6
 MPTS_CHECKPOINTS = 1
 MPTS_GRAPH = 2
 MPTS_AUTOTUNE = 4
+MPTS_LOSS_SQNORM = 0
+MPTS_LOSS_X = 1
+MPTS_LOSS_Y = 2
+MPTS_LOSS_Z = 3
+LOSSES = {"sqnorm": MPTS_LOSS_SQNORM, "x": MPTS_LOSS_X, "y": MPTS_LOSS_Y, "z": MPTS_LOSS_Z}
 
 # every symbol include/mpts.h declares
 SYMBOLS = (
@@ -30,8 +36,9 @@ SYMBOLS = (
     "mpts_bf_from_str", "mpts_bf_from_double", "mpts_bf_to_double", "mpts_set_schedule",
     "mpts_workspace_bytes", "mpts_state_bytes", "mpts_pack_state", "mpts_unpack_state",
     "mpts_integrate", "mpts_integrate_dev", "mpts_check", "mpts_coefficients",
-    "mpts_batch_workspace_bytes", "mpts_integrate_batch", "mpts_grad", "mpts_strerror",
-    "mpts_last_error",
+    "mpts_batch_workspace_bytes", "mpts_integrate_batch", "mpts_grad",
+    "mpts_grad_batch_workspace_bytes", "mpts_grad_batch", "mpts_release_caches",
+    "mpts_strerror", "mpts_last_error",
 )
 
 if not os.path.exists(LIB_PATH):
@@ -74,11 +81,33 @@ _lib.mpts_batch_workspace_bytes.argtypes = [ctypes.POINTER(_P), _i32, ctypes.POI
                                             ctypes.POINTER(_sz)]
 _lib.mpts_integrate_batch.argtypes = [ctypes.POINTER(_P), _i32, _BFP, ctypes.POINTER(_i64), _BFP,
                                       _P, _sz, _P, _u32]
-_lib.mpts_grad.argtypes = [_P, _BFP, _i64, ctypes.POINTER(ctypes.c_double), _BFP, _BFP, _P, _sz, _P]
+_DP = ctypes.POINTER(ctypes.c_double)
+_lib.mpts_grad.argtypes = [_P, _BFP, _i64, _i32, _DP, _DP, _BFP, _BFP, _P, _sz, _P]
+_lib.mpts_grad_batch_workspace_bytes.argtypes = [ctypes.POINTER(_P), _i32, ctypes.POINTER(_i64),
+                                                 ctypes.POINTER(_sz)]
+_lib.mpts_grad_batch.argtypes = [ctypes.POINTER(_P), _i32, _BFP, ctypes.POINTER(_i64), _i32, _DP,
+                                 _DP, _BFP, _P, _sz, _P]
+_lib.mpts_release_caches.argtypes = []
 _lib.mpts_strerror.argtypes = [_i32]
 _lib.mpts_strerror.restype = ctypes.c_char_p
 _lib.mpts_last_error.argtypes = [_P]
 _lib.mpts_last_error.restype = ctypes.c_char_p
+
+
+# Orderly shutdown: at interpreter exit, before the HIP runtime and the
+# library's code objects are torn down, the cached batch graphs are
+# destroyed; from then on no context destructor calls into the library.  The
+# state is bound into Lorenz.__del__ as a default argument, so it is still
+# reachable while the interpreter clears this module's globals.
+_STATE = {"closed": False, "lib": _lib}
+
+
+def _shutdown(state=_STATE):
+    state["lib"].mpts_release_caches()
+    state["closed"] = True
+
+
+atexit.register(_shutdown)
 
 
 class MptsError(RuntimeError):
@@ -159,11 +188,11 @@ class Lorenz:
         self.L, self.p, self.N = Lc.value, pc.value, Nc.value
         self._ws = None
 
-    def __del__(self):
+    def __del__(self, _state=_STATE):
         h = getattr(self, "_h", None)
-        if h:
-            _lib.mpts_destroy(h)
-            self._h = None
+        self._h = None
+        if h and not _state["closed"]:
+            _state["lib"].mpts_destroy(h)
 
     @property
     def handle(self):
@@ -278,19 +307,55 @@ class Lorenz:
                                            ws.numel(), _stream()))
         return tuple([o.get(i) for i in range(self.N + 1)] for o in outs)
 
-    def grad(self, x0, nsteps: int):
-        """Gradient of ||x(T)||^2 w.r.t. (x0, y0, z0, sigma, R, b): returns
-        (6 doubles, 6 big-floats, final state)."""
+    def grad(self, x0, nsteps: int, loss: str = "sqnorm"):
+        """Gradient of a loss of x(T) ("sqnorm": ||x(T)||^2; "x", "y", "z": one
+        component) w.r.t. (x0, y0, z0, sigma, R, b): returns (6 doubles,
+        6 big-floats, final state, loss as a double)."""
         ws = self.workspace(nsteps, MPTS_CHECKPOINTS)
         a = BFArray(3, self.L)
         for j in range(3):
             a.set(j, x0[j])
         g = (ctypes.c_double * 6)()
+        lv = ctypes.c_double()
         gb = BFArray(6, self.L)
         out = BFArray(3, self.L)
-        self._check(_lib.mpts_grad(self._h, a.ptr(), nsteps, g, gb.ptr(), out.ptr(),
-                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
-        return list(g), [gb.get(j) for j in range(6)], [out.get(j) for j in range(3)]
+        self._check(_lib.mpts_grad(self._h, a.ptr(), nsteps, LOSSES[loss], g, ctypes.byref(lv),
+                                   gb.ptr(), out.ptr(), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                   _stream()))
+        return list(g), [gb.get(j) for j in range(6)], [out.get(j) for j in range(3)], lv.value
+
+
+def _batch_bfs(problems, x0s):
+    """mpts_bf arrays of the initial states and of room for the final states
+    (each trajectory with its own limb count), and the storage they use."""
+    n = len(problems)
+    ins = (mpts_bf * (3 * n))()
+    outs = (mpts_bf * (3 * n))()
+    keep = []
+    for t, p in enumerate(problems):
+        for j in range(3):
+            s, m, e = x0s[t][j]
+            buf = (ctypes.c_uint32 * p.L)(*[(m >> (32 * k)) & 0xFFFFFFFF for k in range(p.L)])
+            ob = (ctypes.c_uint32 * p.L)()
+            keep += [buf, ob]
+            ins[3 * t + j].sign, ins[3 * t + j].exp = s, (e if s else 0)
+            ins[3 * t + j].limbs = ctypes.cast(buf, ctypes.POINTER(ctypes.c_uint32))
+            outs[3 * t + j].limbs = ctypes.cast(ob, ctypes.POINTER(ctypes.c_uint32))
+    return ins, outs, keep
+
+
+def _batch_states(problems, outs):
+    res = []
+    for t, p in enumerate(problems):
+        r = []
+        for j in range(3):
+            b = outs[3 * t + j]
+            m = 0
+            for k in range(p.L - 1, -1, -1):
+                m = (m << 32) | b.limbs[k]
+            r.append((int(b.sign), m, int(b.exp)) if b.sign else (0, 0, 0))
+        res.append(r)
+    return res
 
 
 def integrate_batch(problems: Sequence[Lorenz], x0s, nsteps: Sequence[int], flags: int = 0):
@@ -304,48 +369,37 @@ def integrate_batch(problems: Sequence[Lorenz], x0s, nsteps: Sequence[int], flag
     if st != MPTS_OK:
         raise MptsError(st)
     ws = _workspace(need.value)
-    Ls = [p.L for p in problems]
-    Lmax = max(Ls)
-    # per-trajectory limb counts differ: one storage per trajectory
-    ins = (mpts_bf * (3 * n))()
-    outs = (mpts_bf * (3 * n))()
-    keep = []
-    for t, p in enumerate(problems):
-        for j in range(3):
-            s, m, e = x0s[t][j]
-            buf = (ctypes.c_uint32 * p.L)(*[(m >> (32 * k)) & 0xFFFFFFFF for k in range(p.L)])
-            ob = (ctypes.c_uint32 * p.L)()
-            keep += [buf, ob]
-            ins[3 * t + j].sign, ins[3 * t + j].exp = s, (e if s else 0)
-            ins[3 * t + j].limbs = ctypes.cast(buf, ctypes.POINTER(ctypes.c_uint32))
-            outs[3 * t + j].limbs = ctypes.cast(ob, ctypes.POINTER(ctypes.c_uint32))
+    ins, outs, keep = _batch_bfs(problems, x0s)
     st = _lib.mpts_integrate_batch(hs, n, ins, ns, outs, ctypes.c_void_p(ws.data_ptr()),
                                    ws.numel(), _stream(), flags)
     if st != MPTS_OK:
         raise MptsError(st, _lib.mpts_last_error(problems[0].handle).decode())
-    res = []
-    for t, p in enumerate(problems):
-        r = []
-        for j in range(3):
-            b = outs[3 * t + j]
-            m = 0
-            for k in range(p.L - 1, -1, -1):
-                m = (m << 32) | b.limbs[k]
-            r.append((int(b.sign), m, int(b.exp)) if b.sign else (0, 0, 0))
-        res.append(r)
-    del Lmax
-    return res
+    del keep
+    return _batch_states(problems, outs)
 
 
-def _exact_sqnorm(state) -> float:
-    """||x||^2 of a big-float state, computed exactly and rounded once to
-    FP64 (CPython's int/int division is correctly rounded)."""
-    from fractions import Fraction
-    tot = Fraction(0)
-    for (s, m, e) in state:
-        if s:
-            tot += (Fraction(m) * Fraction(2) ** e) ** 2
-    return tot.numerator / tot.denominator
+def grad_batch(problems: Sequence[Lorenz], x0s, nsteps: Sequence[int], loss: str = "sqnorm"):
+    """Gradients of many trajectories (each with its own K, N) in one forward
+    and one reverse launch; returns (grads: count lists of 6 doubles,
+    losses: count doubles, final states)."""
+    n = len(problems)
+    hs = (_P * n)(*[p.handle for p in problems])
+    ns = (_i64 * n)(*nsteps)
+    need = _sz()
+    st = _lib.mpts_grad_batch_workspace_bytes(hs, n, ns, ctypes.byref(need))
+    if st != MPTS_OK:
+        raise MptsError(st)
+    ws = _workspace(need.value)
+    ins, outs, keep = _batch_bfs(problems, x0s)
+    g = (ctypes.c_double * (6 * n))()
+    lv = (ctypes.c_double * n)()
+    st = _lib.mpts_grad_batch(hs, n, ins, ns, LOSSES[loss], g, lv, outs,
+                              ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream())
+    if st != MPTS_OK:
+        raise MptsError(st, _lib.mpts_last_error(problems[0].handle).decode())
+    del keep
+    return ([list(g[6 * t:6 * t + 6]) for t in range(n)], list(lv),
+            _batch_states(problems, outs))
 
 
 def _make_sqnorm_function():
@@ -358,8 +412,8 @@ def _make_sqnorm_function():
         a float64 tensor (sigma, R, b) that must equal the problem's own
         parameters to double precision; the arithmetic uses the problem's
         p-bit parameters (b = 8/3 rounded to p bits, not its double).  The
-        forward value is the FP64 rounding of the exact loss of the p-bit
-        state; backward returns grad_output times the p-bit gradient rounded
+        forward value is the library's FP64 rounding of the exact loss of the
+        p-bit state; backward returns grad_output times the p-bit gradient rounded
         to FP64, for x0 and for params (the b derivative taken at the p-bit b).
         """
 
@@ -370,9 +424,9 @@ def _make_sqnorm_function():
             got = [float(v) for v in params.detach().cpu().tolist()]
             if got != want:
                 raise ValueError(f"params {got} differ from the problem's {want}")
-            g64, _, fin = problem.grad(xs, nsteps)
+            g64, _, _, loss = problem.grad(xs, nsteps, "sqnorm")
             ctx.save_for_backward(torch.tensor(g64, dtype=torch.float64))
-            return torch.tensor(_exact_sqnorm(fin), dtype=torch.float64, device=x0.device)
+            return torch.tensor(loss, dtype=torch.float64, device=x0.device)
 
         @staticmethod
         def backward(ctx, grad_out):
