@@ -98,11 +98,20 @@ def next_coefficients(ctx: Context, a: Sequence[BF], b: Sequence[BF],
     p = ctx.p
     s1 = round_sum(cauchy_terms(a, g, i), p)
     s2 = round_sum(cauchy_terms(a, b, i), p)
+    return tails(ctx, a, b, g, i, s1, s2) + (s1, s2)
+
+
+def tails(ctx: Context, a: Sequence[BF], b: Sequence[BF], g: Sequence[BF], i: int,
+          s1: BF, s2: BF):
+    """alpha_{i+1}, beta_{i+1}, gamma_{i+1} of equation (3) from the
+    coefficients of index i and the rounded Cauchy sums s1_i, s2_i: each
+    numerator exact, divided by i+1 with one rounding."""
+    p = ctx.p
     d = i + 1
     num_a = exact_sum([neg(exact_mul(ctx.sigma, a[i])), exact_mul(ctx.sigma, b[i])])
     num_b = exact_sum([exact_mul(ctx.R, a[i]), neg(exact(b[i])), neg(exact(s1))])
     num_g = exact_sum([exact(s2), neg(exact_mul(ctx.b, g[i]))])
-    return (div_round(num_a, d, p), div_round(num_b, d, p), div_round(num_g, d, p), s1, s2)
+    return (div_round(num_a, d, p), div_round(num_b, d, p), div_round(num_g, d, p))
 
 
 def coefficients(ctx: Context, state: Tuple[BF, BF, BF]):

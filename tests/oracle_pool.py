@@ -112,3 +112,19 @@ def chunked(seq, parts):
     for k, v in enumerate(seq):
         out[k % parts].append(v)
     return [o for o in out if o]
+
+
+def run_task(L, N, x0, nsteps):
+    """The oracle's final state after nsteps steps from x0 ((s, m, e) tuples)."""
+    from oracle import lorenz as lz
+    ctx = _ctx(L, N)
+    fin = lz.integrate(ctx, tuple(_bf(v) for v in x0), nsteps)
+    return [tuple(v) for v in fin]
+
+
+def adjoint_task(L, N, x0, nsteps, loss="sqnorm"):
+    """The oracle's final state and six p-bit gradients of `loss`."""
+    from oracle import adjoint as oad
+    ctx = _ctx(L, N)
+    xT, g = oad.grad(ctx, tuple(_bf(v) for v in x0), nsteps, loss)
+    return [tuple(v) for v in xT], [tuple(v) for v in g]

@@ -202,3 +202,18 @@ def test_paper_verification_rerun_agreement():
                 assert dig >= bound, (n, dig, bound)
                 worst = dig if worst is None else min(worst, dig)
     assert worst is not None and worst > 20
+
+
+def test_parallel_oracle_matches_single_process():
+    """The Cauchy sums split over worker processes into exact partials (the
+    paper's per-thread containers, Section 4), added and rounded once by the
+    master, give the single-process oracle's coefficients bit for bit, for
+    several worker counts (including more workers than terms)."""
+    from oracle.parallel import ParallelOracle
+    ctx = lz.make_context(K_digits=60, N=30)
+    x0 = lz.state_from_strings(ctx, ("-15.8", "-17.48", "35.64"))
+    a, b, g, _, _ = lz.coefficients(ctx, x0)
+    for workers in (1, 3, 5):
+        with ParallelOracle(ctx, workers) as po:
+            pa, pb, pg = po.coefficients(x0)
+        assert (pa, pb, pg) == (a, b, g), workers
