@@ -2,21 +2,22 @@
 """Benchmark: Taylor steps per second of the multiple-precision Taylor series
 method for the Lorenz system on one MI355X.
 
-Default workload lorenz_k2000_n600: sigma=10, R=28, b=8/3 (rounded to p
-bits), K=2000 decimal digits (L=208 32-bit limbs, p=6656 bits), Taylor order
-N=600, tau=1/100, one trajectory from the seeded initial state (seed 2,
-uniform in [-20,20]x[-25,25]x[5,45]).  A "step" is one whole Taylor step:
-the N coefficients of the Leibniz recursion (equation (3)) with their Cauchy
-sums, and the Horner evaluation of the series (equation (2)).
+Default workload lorenz_k4000_n3500: sigma=10, R=28, b=8/3 (rounded to p
+bits), K=4000 decimal digits (L=416 32-bit limbs, p=13312 bits), Taylor
+order N=3500, tau=1/100, one trajectory from (-15.8, -17.48, 35.64) (the
+paper's benchmark initial state, Section 5).  A "step" is one whole Taylor
+step: the N coefficients of the Leibniz recursion (equation (3)) with their
+Cauchy sums, and the Horner evaluation of the series (equation (2)).
 
 The timed region is one device-resident persistent launch of `--steps`
 steps (inputs already in HBM), bracketed by synchronisations and timed with
 events on the launch stream.  Prints one JSON line.
 
 Other modes (reported separately, not the headline line):
-  --workload lorenz_k100_n40 | lorenz_k4000_n3500   other single trajectories
+  --workload lorenz_k2000_n600 | lorenz_k100_n40   other single trajectories
   --mode adjoint     forward-with-checkpoints vs reverse-sweep time (K=300, N=90)
   --mode batch       256-trajectory ensemble in one launch vs one launch each
+  --mode peak        measured issue rates of v_mad_i64_i32 and the int8 MFMA
   --copy-calibration one device copy of 1 GiB (for counter calibration)
 """
 import argparse
@@ -31,6 +32,8 @@ sys.path.insert(0, ROOT)
 # 32x32-bit multiply-adds per second at the full VALU issue rate:
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 INT_VALU_PEAK = 256 * 4 * 16 * 2.4e9
+# dense int8 matrix-core multiply-adds per second (5.0 POPS / 2)
+MFMA_I8_PEAK = 2.5e15
 
 SINGLE = {
     "lorenz_k2000_n600": dict(K=2000, N=600, x0="seed2"),
@@ -54,25 +57,50 @@ def initial_state(kind):
     return ("str", BENCH_X0)
 
 
-def oracle_baseline(workload: str, seconds_budget: float = 20.0):
-    """The oracle, as it stands, on this host: whole steps of the same
-    workload until the budget is used (at least one)."""
+def cpu_model() -> str:
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_baseline(workload: str, seconds_budget: float = 15.0):
+    """The oracle on this host's cores: the coefficient recursion of step 0
+    with each Cauchy sum split over worker processes into exact partials,
+    added and rounded once by the master (the paper's reduction, Section 4;
+    same bits as the single-process oracle).  Indices 0, 1, 2, ... are run
+    until the budget is spent; the rate in limb products per second, divided
+    by the N(N+5) products of a whole step, gives steps per second."""
     from oracle import lorenz as lz
+    from oracle.parallel import ParallelOracle
     from workloads import double_strings
     w = SINGLE[workload]
     ctx = lz.make_context(K_digits=w["K"], N=w["N"])
     kind, v = initial_state(w["x0"])
     s = lz.state_from_strings(ctx, double_strings(v) if kind == "double" else v)
-    n = 0
-    t0 = time.perf_counter()
-    while True:
-        s = lz.step(ctx, s)
-        n += 1
-        dt = time.perf_counter() - t0
-        if dt >= seconds_budget or n >= 50:
-            break
-    return {"value": n / dt, "unit": "steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} step(s) of {workload} from its initial state, single-threaded CPython"}
+    workers = max(1, min(os.cpu_count() or 1, 64))
+    with ParallelOracle(ctx, workers) as po:
+        # the recursion in chunks of indices, each chunk restarted from
+        # index 0 with a larger prefix, until the budget is spent
+        M = 8
+        while True:
+            t0 = time.perf_counter()
+            po.coefficients(s, upto=min(M, ctx.N))
+            dt = time.perf_counter() - t0
+            if dt >= seconds_budget or M >= ctx.N:
+                break
+            M = min(ctx.N, int(M * max(1.2, min(4.0, (seconds_budget / max(dt, 1e-3)) ** 0.5))))
+    M = min(M, ctx.N)
+    done = M * (M + 1) + M  # Cauchy products and b*g_i of indices 0..M-1
+    per_step = float(ctx.N * (ctx.N + 5))
+    return {"value": done / dt / per_step, "unit": "steps/s", "cores": workers, "kind": "oracle",
+            "cpu": cpu_model(),
+            "sample": f"coefficient indices 0..{M - 1} of step 0 of {workload} ({dt:.1f} s), "
+                      f"Cauchy sums split over {workers} worker processes (exact partials, one "
+                      f"rounding); rate of limb products scaled to the N(N+5) products of a step"}
 
 
 def run_single(args):
@@ -104,6 +132,11 @@ def run_single(args):
     ms = e0.elapsed_time(e1)
     macs = limb_macs_per_step(w["N"], prob.L) * args.steps
     achieved = macs / (ms * 1e-3)
+    nd = (32 * prob.L + 27 + 27) // 28
+    pieces = 4 * nd
+    # algorithmic int8 products of the Cauchy sums' pieces (the part the
+    # matrix cores take when the path uses them)
+    i8 = float(w["N"] * (w["N"] + 1)) * pieces * pieces * args.steps
     line = {
         "metric": "Taylor steps/s at (K,N)",
         "value": args.steps / (ms * 1e-3),
@@ -113,19 +146,22 @@ def run_single(args):
         "warmup": args.warmup,
         "ms_per_step": ms / args.steps,
         "higher_is_better": True,
-        "scaling": "weak",
+        "scaling": "none (one GPU)",
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
         "config": {"workload": args.workload, "K_digits": w["K"], "N": w["N"], "limbs": prob.L,
                    "p_bits": prob.p, "tau": "1/100",
                    "x0": "seed 2, uniform box" if w["x0"] == "seed2" else "(-15.8,-17.48,35.64)",
-                   "workgroups": args.wgs or "all CUs"},
+                   "workgroups": args.wgs or "all CUs",
+                   "early_products": "valu" if os.environ.get("MPTS_EARLY") == "valu" else "mfma"},
         "limb_mac_per_s": achieved,
         "wall_s": wall,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT_VALU_PEAK / 1e12,
                      "unit": "T limb-MAC/s", "frac": achieved / INT_VALU_PEAK,
                      "traffic": traffic_from_profiles(args.workload, args.steps)},
+        "mfma": {"achieved": i8 / (ms * 1e-3) / 1e12, "peak": MFMA_I8_PEAK / 1e12,
+                 "unit": "T int8-MAC/s (Cauchy-sum pieces)", "frac": i8 / (ms * 1e-3) / MFMA_I8_PEAK},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = oracle_baseline(args.workload)
@@ -159,26 +195,45 @@ def traffic_from_profiles(workload: str, steps: int):
 
 
 def run_adjoint(args):
-    """Forward run with checkpoints vs the reverse sweep, K=300, N=90."""
+    """Reverse-sweep cost against the forward run (t(reverse:
+    recompute + adjoint) / t(forward), same steps), for the 16-seed K=300,
+    N=90 batch (one forward launch with checkpoints and one reverse launch,
+    mpts_grad_batch, against the forward-only batch) and for one
+    K=4000/N=3500 trajectory (mpts_grad against mpts_integrate)."""
     import torch
     from paper_1908_09301_amd import mpts
-    from workloads import box_state
-    prob = mpts.Lorenz(K=300, N=90)
-    x0 = [prob.from_double(v) for v in box_state(400)]
+    from workloads import BENCH_X0, box_state
+    out = {"metric": "adjoint/forward ratio"}
     n = args.steps
-    prob.integrate(x0, 2)  # warm up
+    probs = [mpts.Lorenz(K=300, N=90) for _ in range(16)]
+    x0s = [[p.from_double(v) for v in box_state(400 + t)] for t, p in enumerate(probs)]
+    mpts.grad_batch(probs, x0s, [2] * 16)  # warm up
+    mpts.integrate_batch(probs, x0s, [2] * 16)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    prob.integrate(x0, n, checkpoints=True)
+    mpts.integrate_batch(probs, x0s, [n] * 16)
     t_fwd = time.perf_counter() - t0
     t0 = time.perf_counter()
-    prob.grad(x0, n)
+    mpts.grad_batch(probs, x0s, [n] * 16)
     t_grad = time.perf_counter() - t0
-    t_rev = t_grad - t_fwd
-    print(json.dumps({"metric": "adjoint/forward ratio", "workload": "adjoint_k300_n90",
-                      "steps": n, "forward_s": t_fwd, "forward_plus_reverse_s": t_grad,
-                      "reverse_over_forward": t_rev / t_fwd,
-                      "total_over_forward": t_grad / t_fwd}), flush=True)
+    out["adjoint_k300_n90_x16"] = {"steps": n, "forward_s": t_fwd, "forward_plus_reverse_s": t_grad,
+                                   "reverse_over_forward": (t_grad - t_fwd) / t_fwd,
+                                   "total_over_forward": t_grad / t_fwd}
+    m = max(1, min(args.steps, 2))
+    p = mpts.Lorenz(K=4000, N=3500)
+    x0 = [p.from_str(v) for v in BENCH_X0]
+    p.integrate(x0, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p.integrate(x0, m)
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    p.grad(x0, m)
+    t_grad = time.perf_counter() - t0
+    out["lorenz_k4000_n3500"] = {"steps": m, "forward_s": t_fwd, "forward_plus_reverse_s": t_grad,
+                                 "reverse_over_forward": (t_grad - t_fwd) / t_fwd,
+                                 "total_over_forward": t_grad / t_fwd}
+    print(json.dumps(out), flush=True)
 
 
 def run_batch(args):
@@ -222,6 +277,18 @@ def run_batch(args):
           flush=True)
 
 
+def run_peak():
+    """Measured issue rates of the two arithmetic units (registers only)."""
+    from paper_1908_09301_amd import mpts
+    mad = mpts.probe_rate(mpts.MPTS_PROBE_VALU_MAD)
+    i8 = mpts.probe_rate(mpts.MPTS_PROBE_MFMA_I8)
+    print(json.dumps({"metric": "measured peak", "v_mad_i64_i32_per_s": mad,
+                      "v_mad_frac_of_stated": mad / INT_VALU_PEAK,
+                      "mfma_i8_mac_per_s": i8, "mfma_frac_of_stated": i8 / MFMA_I8_PEAK,
+                      "stated_valu_peak": INT_VALU_PEAK, "stated_mfma_i8_peak": MFMA_I8_PEAK}),
+          flush=True)
+
+
 def copy_calibration():
     import torch
     a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -235,12 +302,12 @@ def copy_calibration():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--wgs", type=int, default=0, help="workgroups per trajectory (0: all CUs)")
-    ap.add_argument("--workload", default="lorenz_k2000_n600", choices=sorted(SINGLE))
-    ap.add_argument("--mode", default="single", choices=["single", "adjoint", "batch"])
+    ap.add_argument("--workload", default="lorenz_k4000_n3500", choices=sorted(SINGLE))
+    ap.add_argument("--mode", default="single", choices=["single", "adjoint", "batch", "peak"])
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -255,6 +322,8 @@ def main():
         run_adjoint(args)
     elif args.mode == "batch":
         run_batch(args)
+    elif args.mode == "peak":
+        run_peak()
     else:
         run_single(args)
 

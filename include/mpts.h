@@ -137,6 +137,7 @@ int mpts_integrate_dev(mpts_ctx *ctx, const void *x0_dev, int64_t nsteps,
  * the workspace by the last call (MPTS_OK or MPTS_ERANGE). */
 int mpts_check(mpts_ctx *ctx, void *workspace, void *stream);
 
+
 /* The Taylor coefficients alpha_i, beta_i, gamma_i, i = 0..N (equation (3))
  * of one step from x0, each N+1 arrays of caller-owned mpts_bf (L limbs). */
 int mpts_coefficients(mpts_ctx *ctx, const mpts_bf x0[3], mpts_bf *alpha,
@@ -203,6 +204,21 @@ int mpts_grad_batch(mpts_ctx *const *ctxs, int32_t count, const mpts_bf *x0,
  * evicts the graphs of the context it frees).  For an orderly shutdown
  * before the HIP runtime is torn down; later batch calls re-capture. */
 int mpts_release_caches(void);
+
+/* Measured issue rate of one arithmetic unit on the current device, for the
+ * roofline of the measurement (not part of the method): unit
+ * MPTS_PROBE_VALU_MAD gives 32x32 -> 64-bit signed multiply-adds per
+ * second (v_mad_i64_i32, formed as the 8x8 digit tiles of the product
+ * loop), MPTS_PROBE_MFMA_I8 int8 multiply-adds per second of
+ * v_mfma_i32_32x32x32_i8 (the piece products of the matrix-core path).
+ * out_dev: caller's device scratch of at least 8 * 1024 * (compute units)
+ * bytes (the probe kernels' results, written so they are not optimised
+ * away).  Synchronises `stream`.  Errors: MPTS_EINVAL, MPTS_ENOSPC,
+ * MPTS_EHIP. */
+#define MPTS_PROBE_VALU_MAD 0
+#define MPTS_PROBE_MFMA_I8 1
+int mpts_probe_rate(int32_t unit, double *per_second, void *out_dev, size_t out_bytes,
+                    void *stream);
 
 const char *mpts_strerror(int status);
 /* Text of the last error recorded on this context ("" if none). */

@@ -18,6 +18,7 @@
 #include "../../include/mpts.h"
 #include "mpts_common.h"
 #include "mpts_kernels.h"
+#include "mpts_mfma.h"
 
 using namespace mpts;
 
@@ -336,6 +337,7 @@ double loss_of_state(const int32_t *st, int L, int loss) {
 struct mpts_ctx {
   int L, N, nd, RS, WB, CM;
   uint64_t gen = 0;          // creation number, never reused (keys the graph cache)
+  int mfma = 0;              // early Cauchy products on the int8 matrix cores
   std::vector<int32_t> cn;  // NCONST x (L+2) normalised constants
   int wgs = 0;
   int cus = 0;
@@ -373,7 +375,11 @@ size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 constexpr int kMaxWG = 4096;
 
-Layout layout(const mpts_ctx *c, long long nsteps, bool ckpt, int nwg) {
+// Workspace of one trajectory.  The parts every call uses come first (the
+// batch takes a region up to `inst` per trajectory); the coefficient output
+// of mpts_coefficients (with_coefs) and the checkpoints and adjoint rows of
+// the checkpointed calls (ckpt) follow.
+Layout layout(const mpts_ctx *c, long long nsteps, bool ckpt, int nwg, bool with_coefs = true) {
   Layout l;
   size_t o = 0;
   l.prof = o;
@@ -390,12 +396,12 @@ Layout layout(const mpts_ctx *c, long long nsteps, bool ckpt, int nwg) {
   o = al(o + (size_t)3 * (c->N + 1) * c->RS * 4);
   l.gframes = o;
   o = al(o + (size_t)2 * NFR * c->WB * 8);
-  l.coefs = o;
-  o = al(o + (size_t)3 * (c->N + 1) * (c->L + 2) * 4);
   l.inst = o;
   o = al(o + sizeof(Inst));
   l.wgmap = o;
   o = al(o + (size_t)kMaxWG * 4);
+  l.coefs = o;
+  if (with_coefs) o = al(o + (size_t)3 * (c->N + 1) * (c->L + 2) * 4);
   l.ckpt = o;
   if (ckpt) o = al(o + (size_t)(nsteps + 1) * 3 * (c->L + 2) * 4);
   l.adj = o;
@@ -471,6 +477,10 @@ int make_ctx(const char *sigma, const char *R, const char *b, int L, int N, cons
     delete c;
     return MPTS_EUNSUPPORTED;
   }
+  // MPTS_EARLY=valu keeps the early products on the VALU tiles (both paths
+  // give the same bits; the matrix cores hold rows of up to 495 digits)
+  const char *early = getenv("MPTS_EARLY");
+  c->mfma = mf_fits(c->nd) && !(early && strcmp(early, "valu") == 0);
   c->cn.assign((size_t)NCONST * (L + 2), 0);
   std::vector<int32_t> nv;
   auto put = [&](int idx, const std::vector<int32_t> &v) {
@@ -540,7 +550,7 @@ int run_single(mpts_ctx *c, int mode, long long nsteps, const void *x0_dev, void
   int G = c->wgs > 0 ? c->wgs : default_groups(c);
   G = std::min(G, c->cus * (adj ? std::min(c->max_per_cu, c->max_per_cu_adj) : c->max_per_cu));
   G = std::max(std::min(G, kMaxWG), 1);
-  Layout l = layout(c, nsteps, false, G);
+  Layout l = layout(c, nsteps, false, G, mode == MODE_COEFFS);
   if (ws_bytes < l.total) return set_err(c, MPTS_ENOSPC, "workspace too small");
   char *base = (char *)ws;
   hipError_t e;
@@ -571,6 +581,7 @@ int run_single(mpts_ctx *c, int mode, long long nsteps, const void *x0_dev, void
   I.wg0 = 0;
   I.mode = mode;
   I.loss = loss;
+  I.mfma = c->mfma;
   I.nsteps = nsteps;
   I.rows = (int32_t *)(base + l.rows);
   I.consts = (int32_t *)(base + l.consts);
@@ -617,15 +628,16 @@ int read_status(mpts_ctx *c, void *ws, hipStream_t s) {
       (void)hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev);
       double us = rate > 0 ? 1e3 / rate : 0.0;  // rate in kHz
       static const char *nm[16] = {"setup", "accum", "flush", "wait", "final", "release", "horner",
-                                   "step0", "spare", "f.round1", "f.res2", "f.div", "f.row", "h.prod", "h.setup", "h.round"};
+                                   "step0", "spare", "f.round1", "h.stage", "f.div", "f.row", "h.prod", "h.flush", "h.round"};
       fprintf(stderr, "mpts phases (us):");
       for (int w2 = 0; w2 < 2; ++w2) {
         fprintf(stderr, w2 ? "\n  wg1:" : "\n  leader:");
         for (int j = 0; j < (w2 ? 8 : 16); ++j) fprintf(stderr, " %s=%.1f", nm[j], ph[w2 * PH_NPHASE + j] * us);
         if (w2)
-          fprintf(stderr, " e.build=%.1f e.setup=%.1f e.part=%.1f e.slowest=%.1f",
+          fprintf(stderr, " e.build=%.1f e.setup=%.1f e.stage=%.1f e.mma=%.1f e.flush=%.1f e.bar=%.1f",
                   ph[PH_NPHASE + PH_EBUILD] * us, ph[PH_NPHASE + PH_ESETUP] * us,
-                  ph[PH_NPHASE + 9] * us, ph[PH_NPHASE + 11] * us);
+                  ph[PH_NPHASE + 9] * us, ph[PH_NPHASE + 11] * us, ph[PH_NPHASE + 12] * us,
+                  ph[PH_NPHASE + 13] * us);
       }
       fprintf(stderr, "\n");
       const int G = c->last_G;
@@ -968,6 +980,7 @@ void graph_evict(uint64_t gen) {
 
 }  // namespace
 
+
 // ---------------------------------------------------------------------------
 extern "C" {
 
@@ -1229,6 +1242,7 @@ int mpts_integrate_batch(mpts_ctx *const *ctxs, int32_t count, const mpts_bf *x0
     I.G = G[t];
     I.wg0 = wg;
     I.mode = MODE_INTEGRATE;
+    I.mfma = c->mfma;
     I.nsteps = nsteps[t];
     I.rows = (int32_t *)(rb + l.rows);
     I.consts = (int32_t *)(rb + l.consts);
@@ -1453,6 +1467,7 @@ int mpts_grad_batch(mpts_ctx *const *ctxs, int32_t count, const mpts_bf *x0, con
     I.wg0 = wg;
     I.mode = MODE_INTEGRATE;
     I.loss = loss;
+    I.mfma = c->mfma;
     I.nsteps = nsteps[t];
     I.rows = (int32_t *)(rb + l.rows);
     I.consts = (int32_t *)(rb + l.consts);

@@ -6,6 +6,22 @@
 
 namespace mpts {
 
+// Per-instance launchers (one translation unit per chunk size CM).
+#define MPTS_DECLARE_CM(NS)                                                                     \
+  namespace NS {                                                                                \
+  hipError_t launch_run(const Inst *d_insts, const int *d_wg_inst, int nwg, size_t lds,         \
+                        hipStream_t s, bool cooperative);                                       \
+  hipError_t launch_adj(const Inst *d_insts, const int *d_wg_inst, int nwg, size_t lds,         \
+                        hipStream_t s);                                                         \
+  hipError_t set_lds(size_t lds, bool adjoint);                                                 \
+  hipError_t occupancy(int *nb, size_t lds, bool adjoint);                                      \
+  }
+MPTS_DECLARE_CM(cm4)
+MPTS_DECLARE_CM(cm8)
+MPTS_DECLARE_CM(cm16)
+MPTS_DECLARE_CM(cm32)
+#undef MPTS_DECLARE_CM
+
 // Bytes of dynamic LDS one workgroup of the forward (or adjoint) kernel needs.
 size_t lds_bytes(int L, int N, int RS, int WB, int CM, bool adjoint);
 

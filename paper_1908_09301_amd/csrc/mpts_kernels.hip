@@ -19,6 +19,7 @@
 #include "mpts_wave.h"
 #include "mpts_digits.h"
 #include "mpts_rows.h"
+#include "mpts_mfma.h"
 #include "mpts_kernels.h"
 
 namespace mpts {
@@ -345,7 +346,25 @@ struct Carve {
   int8_t *offs;        // adjoint: per-term offset tables of parts without caches
   int maxn;            // bytes of offs
   int NV;
+  uint8_t *stage;      // followers' MFMA staging buffers (alias tcols .. hrow, extended
+                       // when they need more)
 };
+
+// Bytes of the task columns, task rows and Horner rows (contiguous in the
+// carve), raised to what the MFMA staging buffers need; the adjoint's
+// per-term offset tables alias the task columns (they live from frame setup
+// to the end of the products, the task columns only during finalisation).
+__host__ __device__ inline size_t task_region_bytes(int L, int N, int nd, int RS, int CM,
+                                                   bool adjoint) {
+  const int NV = (L + 2 + 3) & ~3;
+  size_t b = (size_t)3 * 64 * CM * 8 + (size_t)6 * (NV > RS ? NV : RS) * 4 + (size_t)4 * RS * 4;
+  if (mf_fits(nd)) {
+    const size_t st = (size_t)mf_stage_bytes(nd);
+    if (st > b) b = st;
+  }
+  if (adjoint && (size_t)adj_table_bytes(N) > b) b = (size_t)adj_table_bytes(N);
+  return b;
+}
 
 __device__ Carve carve(unsigned char *smem, const Inst &I) {
   Carve c;
@@ -354,13 +373,15 @@ __device__ Carve carve(unsigned char *smem, const Inst &I) {
   unsigned char *p = smem;
   c.lf = (long long *)p;
   p += (size_t)NFR * I.WB * 8;
+  unsigned char *task0 = p;
   c.tcols = (long long *)p;
+  c.stage = (uint8_t *)p;
   p += (size_t)3 * 64 * I.CM * 8;
   c.tnorm = (int32_t *)p;
   c.trow = (int32_t *)p;
   p += (size_t)6 * (NV > I.RS ? NV : I.RS) * 4;
   c.hrow = (int32_t *)p;
-  p += (size_t)4 * I.RS * 4;
+  p = task0 + task_region_bytes(I.L, I.N, I.nd, I.RS, I.CM, I.mode == MODE_ADJOINT);
   c.fs = (FrameSrc *)p;
   p += sizeof(FrameSrc) * (NFR + 2);
   c.fd = (FrameD *)p;
@@ -376,7 +397,7 @@ __device__ Carve carve(unsigned char *smem, const Inst &I) {
   c.hc = (int *)p;
   p += ((size_t)3 * (I.N + 1) + 3 * NCONST) * 4;
   c.maxn = I.mode == MODE_ADJOINT ? adj_table_bytes(I.N) : 0;
-  c.offs = c.maxn ? (int8_t *)p : nullptr;
+  c.offs = c.maxn ? (int8_t *)task0 : nullptr;
   return c;
 }
 
@@ -395,14 +416,15 @@ __device__ __forceinline__ void prof_mark(const Inst &I, const Carve &cv, int ph
   *cv.tmark = t;
 }
 
+#if MPTS_CM == 4
 size_t lds_bytes(int L, int N, int RS, int WB, int CM, bool adjoint) {
-  const int NV = (L + 2 + 3) & ~3;
-  size_t b = (size_t)NFR * WB * 8 + (size_t)3 * 64 * CM * 8 + (size_t)6 * (NV > RS ? NV : RS) * 4 +
-             (size_t)4 * RS * 4 + sizeof(FrameSrc) * (NFR + 2) + sizeof(FrameD) * (NFR + 2) + 96 * 4 +
-             8 + 4 * NFR * 4 + ((size_t)3 * (N + 1) + 3 * NCONST) * 4 +
-             (adjoint ? (size_t)adj_table_bytes(N) : 0);
+  const int nd = digits_per_row(L);
+  size_t b = (size_t)NFR * WB * 8 + task_region_bytes(L, N, nd, RS, CM, adjoint) +
+             sizeof(FrameSrc) * (NFR + 2) + sizeof(FrameD) * (NFR + 2) + 96 * 4 +
+             8 + 4 * NFR * 4 + ((size_t)3 * (N + 1) + 3 * NCONST) * 4;
   return (b + 255) & ~(size_t)255;
 }
+#endif
 
 __device__ __forceinline__ int32_t *row_ptr(const Inst &I, int arr, int idx) {
   return I.rows + ((long long)arr * (I.N + 1) + idx) * I.RS;
@@ -577,8 +599,7 @@ __device__ const long long *group_bulk(const Inst &I, const Carve &cv, int nf, i
                                        GroupSync &gs, uint32_t *err) {
   const int tid = threadIdx.x;
   const int G = I.G, WB = I.WB;
-  frame_setup(cv.fs, cv.fd, nf, I.nd, I.RS, cv.red, cv.offs, cv.maxn, (int *)cv.tcols,
-              3 * 64 * I.CM * 2, err);
+  frame_setup(cv.fs, cv.fd, nf, I.nd, I.RS, cv.red, cv.offs, cv.maxn, err);
   prof_mark(I, cv, PH_SETUP);
   frames_accumulate(cv.fs, cv.fd, nf, I.nd, I.RS, WB, cv.lf, rank, G, cv.span);
   __syncthreads();
@@ -1015,6 +1036,76 @@ __device__ void late_step(const Inst &I, const Carve &cv, int rank, int i, Group
   prof_mark(I, cv, PH_FLUSH);
 }
 
+// Follower: the early part of the two Cauchy frames of index j (terms
+// k = 1..j-1, no row j) on the int8 matrix cores, added into the LDS frames
+// 0 and 1 from their fixed bases (cv.fd[NFR], cv.fd[NFR + 1]).  The terms
+// are dealt to the followers in contiguous ranges; a workgroup stages one
+// term at a time (the next term's digits are loaded while the current one
+// is multiplied) and its wavefronts split the (U block, output tile) pairs.
+// Sets the early column spans of frames 0 and 1.
+__device__ void mfma_early(const Inst &I, const Carve &cv, int rank, int j) {
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int nd = I.nd;
+  const MfGeo g = mf_geo(nd);
+  const int n = j - 1;
+  const unsigned W = (unsigned)(I.G - 1), r = (unsigned)(rank - 1);
+  const int k0 = 1 + (int)(((unsigned long long)n * r) / W);
+  const int k1 = 1 + (int)(((unsigned long long)n * (r + 1)) / W);
+  const l_i32 *ha = (const l_i32 *)hc_row(I, cv, 0), *hb = (const l_i32 *)hc_row(I, cv, 1),
+              *hg = (const l_i32 *)hc_row(I, cv, 2);
+  const int b0 = ((const l_i32 *)&cv.fd[NFR].base)[0], b1 = ((const l_i32 *)&cv.fd[NFR + 1].base)[0];
+  auto offset = [&](int eu, int ev, int base) {
+    if (eu == HZ || ev == HZ) return 0;
+    return min(max(eu + ev - base, 0), 2 * SMAX);
+  };
+  if (tid < 2) {
+    l_i32 *es = (l_i32 *)cv.span + 2 * NFR + 2 * tid;
+    es[0] = 0;
+    es[1] = k1 > k0 ? min(I.WB, 256 * g.NT + 1) : 0;
+  }
+  if (k1 <= k0) return;
+  const MfPairs pr = mf_pairs(g, __builtin_amdgcn_readfirstlane(wave));
+  mf_v16i acc[2][MF_NTMAX];
+#pragma unroll
+  for (int f = 0; f < 2; ++f)
+#pragma unroll
+    for (int q = 0; q < MF_NTMAX; ++q)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[f][q][e] = 0;
+  // phase timers (one thread of the group's first follower): staging (with
+  // the wait for its global loads), barrier, products, flush
+  unsigned long long *tp = (I.prof && rank == 1 && tid == 0) ? I.prof + PH_NPHASE : nullptr;
+  unsigned long long tq = tp ? wall_clock64() : 0;
+  auto mark = [&](int slot) {
+    if (tp) {
+      const unsigned long long now = wall_clock64();
+      tp[slot] += now - tq;
+      tq = now;
+    }
+  };
+  MfPrefetch pf;
+  mf_load(pf, row_ptr(I, 0, j - k0), row_ptr(I, 2, k0), row_ptr(I, 1, k0), nd);
+  int cnt = 0;
+  for (int k = k0; k < k1; ++k) {
+    uint8_t *buf = cv.stage + (size_t)((k - k0) & 1) * g.BUF;
+    const int eu = ha[j - k];
+    mf_store(pf, buf, g, nd, offset(eu, hg[k], b0), offset(eu, hb[k], b1));
+    mark(9);
+    __syncthreads();
+    mark(13);
+    if (k + 1 < k1) mf_load(pf, row_ptr(I, 0, j - k - 1), row_ptr(I, 2, k + 1), row_ptr(I, 1, k + 1), nd);
+    mf_term<2>(acc, buf, g, pr);
+    mark(11);
+    if (++cnt == g.FT) {
+      mf_flush<2>(acc, cv.lf, I.WB, g);
+      cnt = 0;
+      mark(12);
+    }
+  }
+  if (cnt > 0) mf_flush<2>(acc, cv.lf, I.WB, g);
+  mark(12);
+}
+
 // The Taylor coefficients 1..N of one step (equation (3)), rows 0 given.
 //
 // One workgroup: every frame of index i in LDS, then the three
@@ -1044,6 +1135,12 @@ __device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, G
     for (int w = threadIdx.x & 63; w < RS; w += 64) dst[w] = b0[w];
   }
   const int *ha = hc_row(I, cv, 0), *hb = hc_row(I, cv, 1), *hg = hc_row(I, cv, 2);
+  // the followers' staging buffers alias LDS that other phases use: their
+  // zero padding is restored once per step
+  if (I.G > 1 && !leader && I.mfma) {
+    mf_clear(cv.stage, mf_geo(nd));
+    __syncthreads();
+  }
   if (I.G == 1) {
     auto cst = [&](int c) { return I.consts + (size_t)c * RS; };
     for (int i = 0; i < I.N; ++i) {
@@ -1176,8 +1273,11 @@ __device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, G
       prof_mark(I, cv, PH_ESETUP);
       unsigned long long *tp = I.prof && rank == 1 ? I.prof + PH_NPHASE + 9 : nullptr;
       unsigned long long *tmx = (unsigned long long *)(cv.red + 32);
-      frames_accumulate(cv.fs + NFR, cv.fd + NFR, 2, nd, RS, I.WB, cv.lf, rank, I.G,
-                        cv.span + 2 * NFR, true, tp, tmx);
+      if (I.mfma)
+        mfma_early(I, cv, rank, j);
+      else
+        frames_accumulate(cv.fs + NFR, cv.fd + NFR, 2, nd, RS, I.WB, cv.lf, rank, I.G,
+                          cv.span + 2 * NFR, true, tp, tmx);
       __syncthreads();
       if (tp && tid == 0) {
         atomicAdd(tp + 2, *tmx);  // slowest thread's products
@@ -1226,9 +1326,39 @@ __device__ __noinline__ void tau_chains(const Inst &I, const Carve &cv, int coun
     stage(0, tid, WGS);
     __syncthreads();
   }
+  // One chain on this workgroup: tau times h on the int8 matrix cores (tau
+  // staged once as the U operand, h each iteration as the V operand, both as
+  // pieces in the LDS of frames 1..4, which are otherwise idle here and are
+  // cleared again afterwards); else VALU tiles.
+  const MfGeo mg = mf_geo(nd);
+  uint8_t *hst = (uint8_t *)(cv.lf + WB);
+  const int hst_bytes = mg.UBs + mg.VBs;
+  const bool mfh = I.mfma && nc == 1 && mf_fits(nd) && hst_bytes <= (NFR - 1) * WB * 8;
+  MfPairs mpr;
+  if (mfh) {
+    for (int w = tid; w < hst_bytes / 4; w += WGS) ((l_u32 *)hst)[w] = 0u;
+    __syncthreads();
+    mf_stage_lds_row(tau_lds, hst, true, mg, nd);
+    mpr = mf_pairs(mg, __builtin_amdgcn_readfirstlane(wave));
+  }
   for (int it = 0; it < count; ++it) {
     // the previous iteration's rows are complete (its closing barrier)
-    lds_products(tau_lds, cv.hrow + (size_t)c0 * RS, RS, nc, nd, WB, cv.lf);
+    if (mfh) {
+      mf_stage_lds_row(cv.hrow + (size_t)c0 * RS, hst + mg.UBs, false, mg, nd);
+      __syncthreads();
+      sub(10);
+      mf_v16i acc[1][MF_NTMAX];
+#pragma unroll
+      for (int q = 0; q < MF_NTMAX; ++q)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[0][q][e] = 0;
+      mf_term<1>(acc, hst, mg, mpr);
+      sub(13);
+      mf_flush<1>(acc, cv.lf, WB, mg);
+      sub(14);
+    } else {
+      lds_products(tau_lds, cv.hrow + (size_t)c0 * RS, RS, nc, nd, WB, cv.lf);
+    }
     __syncthreads();
     sub(13);
     if (mode == 0 && wave == 3 && it + 1 < count) stage(it + 1, lane, 64);
@@ -1248,10 +1378,17 @@ __device__ __noinline__ void tau_chains(const Inst &I, const Carve &cv, int coun
       if (!ok && lane == 0) atomicOr(err, 2u);
       if (mode == 1) publish_row(h, q_row(I, c, it + 1), RS, I.G > 1);
       int ncol = fdw.nz ? frame_cols(fdw, nd) : 0;
+      // the matrix-core flush can reach the columns up to 256 NT (zeros
+      // beyond the product, but cleared all the same)
+      if (mfh) ncol = min(WB, max(ncol, 256 * mg.NT + 1));
       for (int q = lane; q < ncol; q += 64) ((l_i64 *)cv.lf)[(size_t)wave * WB + q] = 0;
     }
     __syncthreads();
     sub(15);
+  }
+  if (mfh) {
+    for (int w = tid; w < hst_bytes / 4; w += WGS) ((l_u32 *)hst)[w] = 0u;
+    __syncthreads();
   }
 }
 
@@ -1512,59 +1649,35 @@ __global__ void __launch_bounds__(WGS) k_adj(const Inst *__restrict__ insts,
   }
 }
 
-__global__ void k_clear(uint32_t *p, size_t nwords) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (; i < nwords; i += stride) p[i] = 0u;
-}
+// ---------------------------------------------------------------------------
+// Launchers.  This file is compiled once per finalisation chunk size
+// (MPTS_CM = 4, 8, 16 or 32, the largest digit chunk a lane holds), so the
+// kernel instances build in parallel; mpts_dispatch.cpp picks the instance.
+#ifndef MPTS_CM
+#error "compile with -DMPTS_CM=4, 8, 16 or 32"
+#endif
+#define MPTS_CAT2(a, b) a##b
+#define MPTS_CAT(a, b) MPTS_CAT2(a, b)
 
-template <int CM>
-static hipError_t launch_cm(const Inst *d_insts, const int *d_wg_inst, int nwg, size_t lds,
-                            hipStream_t s) {
-  auto kern = k_run<CM>;
+namespace MPTS_CAT(cm, MPTS_CM) {
+
+hipError_t launch_run(const Inst *d_insts, const int *d_wg_inst, int nwg, size_t lds, hipStream_t s,
+                      bool cooperative) {
+  auto kern = k_run<MPTS_CM>;
   hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
-  void *args[] = {(void *)&d_insts, (void *)&d_wg_inst};
-  return hipLaunchCooperativeKernel((const void *)kern, dim3(nwg), dim3(WGS), args, (unsigned)lds,
-                                    s);
-}
-
-template <int CM>
-static hipError_t launch_cm_plain(const Inst *d_insts, const int *d_wg_inst, int nwg, size_t lds,
-                                  hipStream_t s) {
-  auto kern = k_run<CM>;
-  hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
-  if (e != hipSuccess) return e;
+  if (cooperative) {
+    void *args[] = {(void *)&d_insts, (void *)&d_wg_inst};
+    return hipLaunchCooperativeKernel((const void *)kern, dim3(nwg), dim3(WGS), args,
+                                      (unsigned)lds, s);
+  }
   hipLaunchKernelGGL(kern, dim3(nwg), dim3(WGS), lds, s, d_insts, d_wg_inst);
   return hipGetLastError();
 }
 
-hipError_t launch_run(const Inst *d_insts, const int *d_wg_inst, int nwg, int CM, size_t lds,
-                      hipStream_t s, bool cooperative) {
-  if (cooperative) {
-    switch (CM) {
-      case 4: return launch_cm<4>(d_insts, d_wg_inst, nwg, lds, s);
-      case 8: return launch_cm<8>(d_insts, d_wg_inst, nwg, lds, s);
-      case 16: return launch_cm<16>(d_insts, d_wg_inst, nwg, lds, s);
-      case 32: return launch_cm<32>(d_insts, d_wg_inst, nwg, lds, s);
-      default: return hipErrorInvalidValue;
-    }
-  }
-  switch (CM) {
-    case 4: return launch_cm_plain<4>(d_insts, d_wg_inst, nwg, lds, s);
-    case 8: return launch_cm_plain<8>(d_insts, d_wg_inst, nwg, lds, s);
-    case 16: return launch_cm_plain<16>(d_insts, d_wg_inst, nwg, lds, s);
-    case 32: return launch_cm_plain<32>(d_insts, d_wg_inst, nwg, lds, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <int CM>
-static hipError_t launch_adj_cm(const Inst *d_insts, const int *d_wg_inst, int nwg, size_t lds,
-                                hipStream_t s) {
-  auto kern = k_adj<CM>;
+hipError_t launch_adj(const Inst *d_insts, const int *d_wg_inst, int nwg, size_t lds, hipStream_t s) {
+  auto kern = k_adj<MPTS_CM>;
   hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
@@ -1573,31 +1686,23 @@ static hipError_t launch_adj_cm(const Inst *d_insts, const int *d_wg_inst, int n
                                     s);
 }
 
-hipError_t launch_adj(const Inst *d_insts, const int *d_wg_inst, int nwg, int CM, size_t lds,
-                      hipStream_t s) {
-  switch (CM) {
-    case 4: return launch_adj_cm<4>(d_insts, d_wg_inst, nwg, lds, s);
-    case 8: return launch_adj_cm<8>(d_insts, d_wg_inst, nwg, lds, s);
-    case 16: return launch_adj_cm<16>(d_insts, d_wg_inst, nwg, lds, s);
-    case 32: return launch_adj_cm<32>(d_insts, d_wg_inst, nwg, lds, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <int CM>
-static hipError_t set_lds_cm(size_t lds, bool adjoint) {
-  const void *k = adjoint ? (const void *)k_adj<CM> : (const void *)k_run<CM>;
+hipError_t set_lds(size_t lds, bool adjoint) {
+  const void *k = adjoint ? (const void *)k_adj<MPTS_CM> : (const void *)k_run<MPTS_CM>;
   return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-hipError_t set_kernel_lds(int CM, size_t lds, bool adjoint) {
-  switch (CM) {
-    case 4: return set_lds_cm<4>(lds, adjoint);
-    case 8: return set_lds_cm<8>(lds, adjoint);
-    case 16: return set_lds_cm<16>(lds, adjoint);
-    case 32: return set_lds_cm<32>(lds, adjoint);
-    default: return hipErrorInvalidValue;
-  }
+hipError_t occupancy(int *nb, size_t lds, bool adjoint) {
+  if (adjoint) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_adj<MPTS_CM>, WGS, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_run<MPTS_CM>, WGS, lds);
+}
+
+}  // namespace cmN
+
+#if MPTS_CM == 4
+__global__ void k_clear(uint32_t *p, size_t nwords) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < nwords; i += stride) p[i] = 0u;
 }
 
 hipError_t launch_clear(void *p, size_t bytes, hipStream_t s) {
@@ -1608,34 +1713,6 @@ hipError_t launch_clear(void *p, size_t bytes, hipStream_t s) {
   hipLaunchKernelGGL(k_clear, dim3(blocks), dim3(256), 0, s, (uint32_t *)p, words);
   return hipGetLastError();
 }
-
-template <int CM>
-static hipError_t occupancy_cm(int *nb, size_t lds, bool adjoint) {
-  if (adjoint) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_adj<CM>, WGS, lds);
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_run<CM>, WGS, lds);
-}
-
-int max_coresident(int CM, size_t lds, int *out, bool adjoint) {
-  int nb = 0;
-  // the occupancy query honours the kernel's dynamic-LDS limit: raise it first
-  hipError_t e = set_kernel_lds(CM, lds, adjoint);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();  // do not leave the failure for the next launch to report
-    return -1;
-  }
-  switch (CM) {
-    case 4: e = occupancy_cm<4>(&nb, lds, adjoint); break;
-    case 8: e = occupancy_cm<8>(&nb, lds, adjoint); break;
-    case 16: e = occupancy_cm<16>(&nb, lds, adjoint); break;
-    case 32: e = occupancy_cm<32>(&nb, lds, adjoint); break;
-    default: return -1;
-  }
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return -2;
-  }
-  *out = nb;
-  return 0;
-}
+#endif
 
 }  // namespace mpts

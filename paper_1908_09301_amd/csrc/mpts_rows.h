@@ -341,11 +341,12 @@ __device__ __forceinline__ FrameD make_desc(int n, int fbase, int mlo, int mhi, 
 // nonzero terms (one workgroup reduction for all frames).  Exponents come
 // from the parts' caches (LDS) or, for parts without both caches, from the
 // row headers; those parts get a table of per-term digit offsets in LDS
-// (offs, maxn bytes; esum: int scratch of esum_cap entries), so that the
-// product loop never waits on a header load.  Every thread of the
+// (offs, maxn bytes), so that the product loop never waits on a header
+// load.  The exponent sums are read twice (for the reduction, then for the
+// table) rather than kept in a scratch array.  Every thread of the
 // workgroup calls this; thread 0 stores the table slices into fs.
 __device__ void frame_setup(FrameSrc *fs, FrameD *fd, int nf, int nd, int RS, int *red,
-                            int8_t *offs, int maxn, int *esum, int esum_cap, uint32_t *err) {
+                            int8_t *offs, int maxn, uint32_t *err) {
   const int tid = threadIdx.x;
   int mn[NFR], mx[NFR];
   int ob = 0;  // table position of the next uncached part (same in every thread)
@@ -359,10 +360,9 @@ __device__ void frame_setup(FrameSrc *fs, FrameD *fd, int nf, int nd, int RS, in
       for (int j = 0; j < np; ++j) {
         const FramePart q = lds_get(&fs[f].p[j]);
         const bool cached = q.hU && q.hV;
-        if (!cached && (ob + q.n > maxn || ob + q.n > esum_cap)) fits = false;
+        if (!cached && ob + q.n > maxn) fits = false;
         for (int k = tid; k < q.n; k += WGS) {
           const int e = part_esum(q, k, RS);
-          if (!cached && fits) ((l_i32 *)esum)[ob + k] = e;
           if (e != HZ) {
             mn[f] = min(mn[f], e);
             mx[f] = max(mx[f], e);
@@ -397,7 +397,7 @@ __device__ void frame_setup(FrameSrc *fs, FrameD *fd, int nf, int nd, int RS, in
       FramePart &q = fs[f].p[j];
       if (q.hU && q.hV) continue;
       for (int k = tid; k < q.n; k += WGS) {
-        const int e = ((const l_i32 *)esum)[ob + k];
+        const int e = part_esum(q, k, RS);
         ((l_i8 *)offs)[ob + k] = (int8_t)(e == HZ ? 0 : min(max(e - base, 0), S));
       }
       if (tid == 0) q.ot = offs + ob;

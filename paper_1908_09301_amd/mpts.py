@@ -38,7 +38,7 @@ SYMBOLS = (
     "mpts_integrate", "mpts_integrate_dev", "mpts_check", "mpts_coefficients",
     "mpts_batch_workspace_bytes", "mpts_integrate_batch", "mpts_grad",
     "mpts_grad_batch_workspace_bytes", "mpts_grad_batch", "mpts_release_caches",
-    "mpts_strerror", "mpts_last_error",
+    "mpts_probe_rate", "mpts_strerror", "mpts_last_error",
 )
 
 if not os.path.exists(LIB_PATH):
@@ -88,6 +88,7 @@ _lib.mpts_grad_batch_workspace_bytes.argtypes = [ctypes.POINTER(_P), _i32, ctype
 _lib.mpts_grad_batch.argtypes = [ctypes.POINTER(_P), _i32, _BFP, ctypes.POINTER(_i64), _i32, _DP,
                                  _DP, _BFP, _P, _sz, _P]
 _lib.mpts_release_caches.argtypes = []
+_lib.mpts_probe_rate.argtypes = [_i32, _DP, _P, _sz, _P]
 _lib.mpts_strerror.argtypes = [_i32]
 _lib.mpts_strerror.restype = ctypes.c_char_p
 _lib.mpts_last_error.argtypes = [_P]
@@ -323,6 +324,24 @@ class Lorenz:
                                    gb.ptr(), out.ptr(), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                    _stream()))
         return list(g), [gb.get(j) for j in range(6)], [out.get(j) for j in range(3)], lv.value
+
+
+MPTS_PROBE_VALU_MAD = 0
+MPTS_PROBE_MFMA_I8 = 1
+
+
+def probe_rate(unit: int) -> float:
+    """Measured multiply-adds per second of one arithmetic unit
+    (MPTS_PROBE_VALU_MAD or MPTS_PROBE_MFMA_I8) on the current device."""
+    import torch
+    n = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+    out = _workspace(8 * 1024 * n)
+    v = ctypes.c_double()
+    st = _lib.mpts_probe_rate(unit, ctypes.byref(v), ctypes.c_void_p(out.data_ptr()), out.numel(),
+                              _stream())
+    if st != MPTS_OK:
+        raise MptsError(st)
+    return v.value
 
 
 def _batch_bfs(problems, x0s):

@@ -71,3 +71,64 @@ def test_invalid_arguments_fail_cleanly():
     p = mpts.Lorenz(L=4, N=3)
     with pytest.raises(mpts.MptsError):
         p.from_str("1/0")
+
+
+def test_agreement_digits_exact():
+    """The clean-numerical-simulation comparison of two states: -log10 of the
+    largest relative difference, on the exact values."""
+    from paper_1908_09301_amd.cns import agreement_digits
+    one = (1, 1 << 63, -63)             # 1
+    near = (1, (1 << 63) + 1, -63)      # 1 + 2^-63
+    two = (1, 1 << 63, -62)             # 2
+    assert agreement_digits([one, one, one], [one, one, one], 40.0) == 40.0
+    d = agreement_digits([near, one, two], [one, one, two], 40.0)
+    assert abs(d - 63 * 0.30102999566398120) < 1e-9
+    assert agreement_digits([two, one, one], [one, one, one], 40.0) == 0.0
+
+
+def test_error_paths_before_any_device_work():
+    """Bad arguments are refused on the host with their codes: strings, sizes,
+    unnormalised big-floats, a workspace smaller than the call needs."""
+    import ctypes
+    mpts = _lib()
+    lib = mpts._lib
+    h = ctypes.c_void_p()
+    assert lib.mpts_create(b"10", b"28", b"8/3", 0, 40, b"1/100", ctypes.byref(h)) == mpts.MPTS_EINVAL
+    assert lib.mpts_create(b"10", b"28", b"8/3", 100, 0, b"1/100", ctypes.byref(h)) == mpts.MPTS_EINVAL
+    assert lib.mpts_create(b"1o", b"28", b"8/3", 100, 40, b"1/100", ctypes.byref(h)) == mpts.MPTS_EINVAL
+    assert lib.mpts_create(b"10", b"28", b"8/0", 100, 40, b"1/100", ctypes.byref(h)) == mpts.MPTS_EINVAL
+    p = mpts.Lorenz(K=100, N=40)
+    x = mpts.BFArray(3, p.L)
+    for j, v in enumerate(BENCH_X0):
+        x.set(j, p.from_str(v))
+    out = mpts.BFArray(3, p.L)
+    need = p.workspace_bytes(10)
+    # workspace one byte short: refused before any device call
+    st = lib.mpts_integrate(p.handle, x.ptr(), 10, out.ptr(), None, ctypes.c_void_p(1 << 20),
+                            need - 1, None, 0)
+    assert st == mpts.MPTS_ENOSPC
+    assert b"workspace" in lib.mpts_last_error(p.handle)
+    # negative step count
+    st = lib.mpts_integrate(p.handle, x.ptr(), -1, out.ptr(), None, ctypes.c_void_p(1 << 20),
+                            need, None, 0)
+    assert st == mpts.MPTS_EINVAL
+    # an unnormalised mantissa (top bit clear) and a bad sign
+    s, m, e = p.from_str("1.5")
+    x.set(0, (s, m >> 1, e + 1))
+    st = lib.mpts_integrate(p.handle, x.ptr(), 1, out.ptr(), None, ctypes.c_void_p(1 << 20),
+                            need, None, 0)
+    assert st == mpts.MPTS_EINVAL
+    x.set(0, (s, m, e))
+    x.arr[0].sign = 2
+    st = lib.mpts_integrate(p.handle, x.ptr(), 1, out.ptr(), None, ctypes.c_void_p(1 << 20),
+                            need, None, 0)
+    assert st == mpts.MPTS_EINVAL
+    # checkpoints without the flag, an unknown loss
+    ck = mpts.BFArray(3 * 2, p.L)
+    st = lib.mpts_integrate(p.handle, x.ptr(), 1, out.ptr(), ck.ptr(), ctypes.c_void_p(1 << 20),
+                            need, None, 0)
+    assert st == mpts.MPTS_EINVAL
+    g = (ctypes.c_double * 6)()
+    st = lib.mpts_grad(p.handle, x.ptr(), 1, 7, g, None, None, None, ctypes.c_void_p(1 << 20),
+                       need, None)
+    assert st == mpts.MPTS_EINVAL

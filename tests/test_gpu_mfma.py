@@ -1,0 +1,92 @@
+"""The early Cauchy products on the int8 matrix cores (7-bit pieces, Toeplitz
+blocks, i32 accumulators flushed into 64-bit columns) against the oracle and
+against the VALU tile path, bit for bit (GPU).
+
+MPTS_EARLY=valu, read when a context is created, selects the VALU tiles;
+by default a context whose rows fit the matrix-core accumulators (at most
+495 digits, L <= 432 limbs) uses the matrix cores whenever its trajectory
+runs on two or more workgroups."""
+import os
+import sys
+
+import pytest
+
+from oracle import lorenz as lz
+from workloads import BENCH_X0, box_state, double_strings
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def make(gpu_lib, path, **kw):
+    old = os.environ.get("MPTS_EARLY")
+    try:
+        if path == "valu":
+            os.environ["MPTS_EARLY"] = "valu"
+        else:
+            os.environ.pop("MPTS_EARLY", None)
+        return gpu_lib.Lorenz(**kw)
+    finally:
+        if old is None:
+            os.environ.pop("MPTS_EARLY", None)
+        else:
+            os.environ["MPTS_EARLY"] = old
+
+
+# (L, N, workgroups): one output tile (L <= 84), two, three and four tiles
+# (L = 208, 416, 432: the largest size the accumulators hold), one follower
+# doing every term (G = 2: several accumulator flushes per index at L = 416),
+# odd and XCD-sized groups
+CASES = [(1, 9, 3), (4, 30, 7), (12, 40, 24), (22, 60, 16), (42, 70, 5), (84, 60, 33),
+         (168, 50, 64), (208, 40, 256), (416, 30, 256), (432, 20, 100), (416, 150, 2)]
+
+
+@pytest.mark.parametrize("L,N,wgs", CASES)
+def test_mfma_coefficients_match_oracle(gpu_lib, L, N, wgs):
+    say("mfma coefficients", L, N, wgs)
+    ctx = lz.make_context(L=L, N=N)
+    x0 = lz.state_from_strings(ctx, double_strings(box_state(20 + L)))
+    a, b, g, _, _ = lz.coefficients(ctx, x0)
+    p = make(gpu_lib, "mfma", L=L, N=N)
+    p.set_schedule(wgs)
+    ga, gb, gg = p.coefficients([tuple(v) for v in x0])
+    for name, ref, got in (("alpha", a, ga), ("beta", b, gb), ("gamma", g, gg)):
+        for i, (r, q) in enumerate(zip(ref, got)):
+            assert tuple(r) == q, (name, i)
+
+
+@pytest.mark.parametrize("L,N,wgs,steps", [(12, 40, 7, 30), (84, 120, 64, 4), (208, 600, 256, 3),
+                                           (416, 400, 256, 2)])
+def test_mfma_and_valu_paths_give_the_same_bits(gpu_lib, L, N, wgs, steps):
+    say("mfma vs valu", L, N, wgs, steps)
+    x0 = None
+    out = []
+    for path in ("mfma", "valu"):
+        p = make(gpu_lib, path, L=L, N=N)
+        p.set_schedule(wgs)
+        if x0 is None:
+            x0 = [p.from_str(v) for v in BENCH_X0]
+        out.append(p.integrate(x0, steps))
+    assert out[0] == out[1]
+
+
+def test_mfma_z_axis_and_spread_error(gpu_lib):
+    """Zero rows (x = y = 0) on the matrix-core path, and a spread beyond the
+    device window still reported as MPTS_ERANGE."""
+    from oracle.bigfloat import ZERO
+    ctx = lz.make_context(L=12, N=40)
+    x0 = (ZERO, ZERO, lz.state_from_strings(ctx, ("0", "0", "35.64"))[2])
+    ref = lz.integrate(ctx, x0, 5)
+    p = make(gpu_lib, "mfma", L=12, N=40)
+    p.set_schedule(16)
+    assert p.integrate([tuple(v) for v in x0], 5) == [tuple(v) for v in ref]
+    q = make(gpu_lib, "mfma", L=4, N=4)
+    q.set_schedule(9)
+    bad = lz.state_from_strings(lz.make_context(L=4, N=4), ("1e-200", "1", "1"))
+    with pytest.raises(gpu_lib.MptsError) as ei:
+        q.integrate([tuple(v) for v in bad], 1)
+    assert ei.value.code == gpu_lib.MPTS_ERANGE
