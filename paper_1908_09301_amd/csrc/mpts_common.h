@@ -66,7 +66,7 @@ struct Inst {
   int G, wg0;                // workgroups of the group and the first one
   int mode;
   int loss;           // adjoint seed: 0 = 2 x(T) (squared norm), 1..3 = unit vector e_x, e_y, e_z
-  int mfma;           // early Cauchy products on the int8 matrix cores (else VALU tiles)
+  int mfma;           // bit 0: early Cauchy products on the int8 matrix cores (else VALU tiles)
   int pad1;
   long long nsteps;
   int32_t *rows;      // [3][N+1][RS]

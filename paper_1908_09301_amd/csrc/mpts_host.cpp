@@ -337,7 +337,7 @@ double loss_of_state(const int32_t *st, int L, int loss) {
 struct mpts_ctx {
   int L, N, nd, RS, WB, CM;
   uint64_t gen = 0;          // creation number, never reused (keys the graph cache)
-  int mfma = 0;              // early Cauchy products on the int8 matrix cores
+  int mfma = 0;              // 1: early Cauchy products on the int8 matrix cores
   std::vector<int32_t> cn;  // NCONST x (L+2) normalised constants
   int wgs = 0;
   int cus = 0;
@@ -480,7 +480,7 @@ int make_ctx(const char *sigma, const char *R, const char *b, int L, int N, cons
   // MPTS_EARLY=valu keeps the early products on the VALU tiles (both paths
   // give the same bits; the matrix cores hold rows of up to 495 digits)
   const char *early = getenv("MPTS_EARLY");
-  c->mfma = mf_fits(c->nd) && !(early && strcmp(early, "valu") == 0);
+  c->mfma = mf_fits(c->nd) && !(early && strcmp(early, "valu") == 0) ? 1 : 0;
   c->cn.assign((size_t)NCONST * (L + 2), 0);
   std::vector<int32_t> nv;
   auto put = [&](int idx, const std::vector<int32_t> &v) {
@@ -628,7 +628,7 @@ int read_status(mpts_ctx *c, void *ws, hipStream_t s) {
       (void)hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev);
       double us = rate > 0 ? 1e3 / rate : 0.0;  // rate in kHz
       static const char *nm[16] = {"setup", "accum", "flush", "wait", "final", "release", "horner",
-                                   "step0", "spare", "f.round1", "h.stage", "f.div", "f.row", "h.prod", "h.flush", "h.round"};
+                                   "step0", "spare", "f.round1", "f.res2", "f.div", "f.row", "h.prod", "h.setup", "h.round"};
       fprintf(stderr, "mpts phases (us):");
       for (int w2 = 0; w2 < 2; ++w2) {
         fprintf(stderr, w2 ? "\n  wg1:" : "\n  leader:");

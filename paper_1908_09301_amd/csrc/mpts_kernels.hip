@@ -1137,7 +1137,7 @@ __device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, G
   const int *ha = hc_row(I, cv, 0), *hb = hc_row(I, cv, 1), *hg = hc_row(I, cv, 2);
   // the followers' staging buffers alias LDS that other phases use: their
   // zero padding is restored once per step
-  if (I.G > 1 && !leader && I.mfma) {
+  if (I.G > 1 && !leader && (I.mfma & 1)) {
     mf_clear(cv.stage, mf_geo(nd));
     __syncthreads();
   }
@@ -1273,7 +1273,7 @@ __device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, G
       prof_mark(I, cv, PH_ESETUP);
       unsigned long long *tp = I.prof && rank == 1 ? I.prof + PH_NPHASE + 9 : nullptr;
       unsigned long long *tmx = (unsigned long long *)(cv.red + 32);
-      if (I.mfma)
+      if (I.mfma & 1)
         mfma_early(I, cv, rank, j);
       else
         frames_accumulate(cv.fs + NFR, cv.fd + NFR, 2, nd, RS, I.WB, cv.lf, rank, I.G,
@@ -1326,39 +1326,9 @@ __device__ __noinline__ void tau_chains(const Inst &I, const Carve &cv, int coun
     stage(0, tid, WGS);
     __syncthreads();
   }
-  // One chain on this workgroup: tau times h on the int8 matrix cores (tau
-  // staged once as the U operand, h each iteration as the V operand, both as
-  // pieces in the LDS of frames 1..4, which are otherwise idle here and are
-  // cleared again afterwards); else VALU tiles.
-  const MfGeo mg = mf_geo(nd);
-  uint8_t *hst = (uint8_t *)(cv.lf + WB);
-  const int hst_bytes = mg.UBs + mg.VBs;
-  const bool mfh = I.mfma && nc == 1 && mf_fits(nd) && hst_bytes <= (NFR - 1) * WB * 8;
-  MfPairs mpr;
-  if (mfh) {
-    for (int w = tid; w < hst_bytes / 4; w += WGS) ((l_u32 *)hst)[w] = 0u;
-    __syncthreads();
-    mf_stage_lds_row(tau_lds, hst, true, mg, nd);
-    mpr = mf_pairs(mg, __builtin_amdgcn_readfirstlane(wave));
-  }
   for (int it = 0; it < count; ++it) {
     // the previous iteration's rows are complete (its closing barrier)
-    if (mfh) {
-      mf_stage_lds_row(cv.hrow + (size_t)c0 * RS, hst + mg.UBs, false, mg, nd);
-      __syncthreads();
-      sub(10);
-      mf_v16i acc[1][MF_NTMAX];
-#pragma unroll
-      for (int q = 0; q < MF_NTMAX; ++q)
-#pragma unroll
-        for (int e = 0; e < 16; ++e) acc[0][q][e] = 0;
-      mf_term<1>(acc, hst, mg, mpr);
-      sub(13);
-      mf_flush<1>(acc, cv.lf, WB, mg);
-      sub(14);
-    } else {
-      lds_products(tau_lds, cv.hrow + (size_t)c0 * RS, RS, nc, nd, WB, cv.lf);
-    }
+    lds_products(tau_lds, cv.hrow + (size_t)c0 * RS, RS, nc, nd, WB, cv.lf);
     __syncthreads();
     sub(13);
     if (mode == 0 && wave == 3 && it + 1 < count) stage(it + 1, lane, 64);
@@ -1378,17 +1348,10 @@ __device__ __noinline__ void tau_chains(const Inst &I, const Carve &cv, int coun
       if (!ok && lane == 0) atomicOr(err, 2u);
       if (mode == 1) publish_row(h, q_row(I, c, it + 1), RS, I.G > 1);
       int ncol = fdw.nz ? frame_cols(fdw, nd) : 0;
-      // the matrix-core flush can reach the columns up to 256 NT (zeros
-      // beyond the product, but cleared all the same)
-      if (mfh) ncol = min(WB, max(ncol, 256 * mg.NT + 1));
       for (int q = lane; q < ncol; q += 64) ((l_i64 *)cv.lf)[(size_t)wave * WB + q] = 0;
     }
     __syncthreads();
     sub(15);
-  }
-  if (mfh) {
-    for (int w = tid; w < hst_bytes / 4; w += WGS) ((l_u32 *)hst)[w] = 0u;
-    __syncthreads();
   }
 }
 

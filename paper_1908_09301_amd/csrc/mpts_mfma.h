@@ -165,6 +165,9 @@ __device__ __forceinline__ void mf_store(const MfPrefetch &r, uint8_t *buf, cons
 // 8 bytes from LDS at any byte address (gfx950 reads unaligned LDS words
 // in one ds_read_b64).
 typedef __attribute__((address_space(3), aligned(1))) uint64_t l_u64u;
+// 8 bytes from LDS at any byte address (gfx950 reads unaligned LDS words
+// in one ds_read_b64).
+typedef __attribute__((address_space(3), aligned(1))) uint64_t l_u64u;
 // Stage a digit row held in LDS (header, RPAD zero digits, nd digits) as
 // pieces: reversed into a U buffer, or at offset 0 into a V buffer (whose
 // other slots must already be zero).  Every thread of the workgroup.
@@ -186,7 +189,8 @@ __device__ __forceinline__ uint64_t mf_ld64(const l_u8 *p) { return *(const l_u6
 // wavefront w takes pairs [P w / 4, P (w+1) / 4).  All of it is uniform over
 // the wavefront (scalar registers): `wave` comes through readfirstlane.
 struct MfPairs {
-  int plo, phi;
+  int m0, m1;    // first and last U block with pairs of this wavefront (m0 > m1: none)
+  int qa0, qb1;  // first tile of block m0 and last tile of block m1 that are its pairs
 };
 
 __device__ __forceinline__ void mf_qrange(const MfGeo &g, int m, int *qlo, int *qhi) {
@@ -205,9 +209,27 @@ __device__ __forceinline__ MfPairs mf_pairs(const MfGeo &g, int wave) {
     mf_qrange(g, m, &lo, &hi);
     P += hi >= lo ? hi - lo + 1 : 0;
   }
+  const int plo = P * wave / 4, phi = P * (wave + 1) / 4;
   MfPairs r;
-  r.plo = P * wave / 4;
-  r.phi = P * (wave + 1) / 4;
+  r.m0 = 0;
+  r.m1 = -1;
+  r.qa0 = r.qb1 = 0;
+  int pi = 0;
+  for (int m = 0; m < g.MM; ++m) {
+    int lo, hi;
+    mf_qrange(g, m, &lo, &hi);
+    for (int q = lo; q <= hi; ++q, ++pi) {
+      if (pi == plo) {
+        r.m0 = m;
+        r.qa0 = q;
+      }
+      if (pi == phi - 1) {
+        r.m1 = m;
+        r.qb1 = q;
+      }
+    }
+  }
+  if (phi <= plo) r.m1 = -1;
   return r;
 }
 
@@ -265,6 +287,14 @@ __device__ __forceinline__ void mf_stage_mma(mf_v16i (&acc)[NF][MF_NTMAX], const
   }
 }
 
+// Tiles of block m among this wavefront's pairs.
+__device__ __forceinline__ void mf_qclip(const MfGeo &g, const MfPairs &pr, int m, int *qlo,
+                                         int *qhi) {
+  mf_qrange(g, m, qlo, qhi);
+  if (m == pr.m0) *qlo = pr.qa0;
+  if (m == pr.m1) *qhi = pr.qb1;
+}
+
 template <int NF>
 __device__ __forceinline__ void mf_term(mf_v16i (&acc)[NF][MF_NTMAX], const uint8_t *buf,
                                         const MfGeo &g, const MfPairs &pr) {
@@ -274,38 +304,27 @@ __device__ __forceinline__ void mf_term(mf_v16i (&acc)[NF][MF_NTMAX], const uint
   // per-lane parts of the addresses
   const l_u8 *wbase = U + g.ZU - t + 16 * h;
   const int xl = 36 * (t + MF_VLO / 32) + 16 * h;
-  // walk the pairs in (m, q) order up to this wavefront's range
-  int pi = 0, m = 0;
-  for (; m < g.MM; ++m) {
-    int lo, hi;
-    mf_qrange(g, m, &lo, &hi);
-    const int n = hi >= lo ? hi - lo + 1 : 0;
-    if (pi + n > pr.plo) break;
-    pi += n;
-  }
-  if (m >= g.MM || pi >= pr.phi) return;
-  // q range of block m restricted to this wavefront's pairs
-  auto clip = [&](int mm, int base, int *qlo, int *qhi) {
-    int lo, hi;
-    mf_qrange(g, mm, &lo, &hi);
-    const int a = max(lo, lo + (pr.plo - base)), b = min(hi, lo + (pr.phi - 1 - base));
-    *qlo = a;
-    *qhi = b;
-    return hi >= lo ? hi - lo + 1 : 0;
-  };
-  MfStage<NF> cur, nxt;
+  const int m0 = __builtin_amdgcn_readfirstlane(pr.m0), m1 = __builtin_amdgcn_readfirstlane(pr.m1);
+  if (m0 > m1) return;
+  // two register stages in turn: the operands of the next block are loaded
+  // (unconditionally, the last block again at the end, so that the number of
+  // reads in flight is fixed) while the current block's products issue
+  MfStage<NF> A, B;
   int qa, qb;
-  int n = clip(m, pi, &qa, &qb);
-  mf_stage_load<NF>(cur, wbase, V0, V1, xl, m, qa, qb);
-  pi += n;
-  for (++m; m < g.MM && pi < pr.phi; ++m) {
-    n = clip(m, pi, &qa, &qb);
-    mf_stage_load<NF>(nxt, wbase, V0, V1, xl, m, qa, qb);
-    mf_stage_mma<NF>(acc, cur);
-    cur = nxt;
-    pi += n;
+  mf_qclip(g, pr, m0, &qa, &qb);
+  mf_stage_load<NF>(A, wbase, V0, V1, xl, m0, qa, qb);
+  for (int m = m0;; m += 2) {
+    const int mb = m + 1 < m1 ? m + 1 : m1;
+    mf_qclip(g, pr, mb, &qa, &qb);
+    mf_stage_load<NF>(B, wbase, V0, V1, xl, mb, qa, qb);
+    mf_stage_mma<NF>(acc, A);
+    if (m + 1 > m1) break;
+    const int ma = m + 2 < m1 ? m + 2 : m1;
+    mf_qclip(g, pr, ma, &qa, &qb);
+    mf_stage_load<NF>(A, wbase, V0, V1, xl, ma, qa, qb);
+    mf_stage_mma<NF>(acc, B);
+    if (m + 2 > m1) break;
   }
-  mf_stage_mma<NF>(acc, cur);
 }
 
 // Add the accumulators into the frames' 64-bit LDS columns lf[f * WB + c]

@@ -23,18 +23,22 @@ def say(*a):
 
 
 def make(gpu_lib, path, **kw):
-    old = os.environ.get("MPTS_EARLY")
+    """A context on the given path: "early" (matrix cores for the early
+    products) or "valu"."""
+    keys = ("MPTS_EARLY",)
+    old = {k: os.environ.get(k) for k in keys}
     try:
+        for k in keys:
+            os.environ.pop(k, None)
         if path == "valu":
             os.environ["MPTS_EARLY"] = "valu"
-        else:
-            os.environ.pop("MPTS_EARLY", None)
         return gpu_lib.Lorenz(**kw)
     finally:
-        if old is None:
-            os.environ.pop("MPTS_EARLY", None)
-        else:
-            os.environ["MPTS_EARLY"] = old
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
 
 
 # (L, N, workgroups): one output tile (L <= 84), two, three and four tiles
@@ -51,7 +55,7 @@ def test_mfma_coefficients_match_oracle(gpu_lib, L, N, wgs):
     ctx = lz.make_context(L=L, N=N)
     x0 = lz.state_from_strings(ctx, double_strings(box_state(20 + L)))
     a, b, g, _, _ = lz.coefficients(ctx, x0)
-    p = make(gpu_lib, "mfma", L=L, N=N)
+    p = make(gpu_lib, "early", L=L, N=N)
     p.set_schedule(wgs)
     ga, gb, gg = p.coefficients([tuple(v) for v in x0])
     for name, ref, got in (("alpha", a, ga), ("beta", b, gb), ("gamma", g, gg)):
@@ -59,13 +63,27 @@ def test_mfma_coefficients_match_oracle(gpu_lib, L, N, wgs):
             assert tuple(r) == q, (name, i)
 
 
+@pytest.mark.parametrize("L,N,wgs", [(416, 400, 256), (432, 300, 64)])
+def test_mfma_and_valu_coefficients_agree(gpu_lib, L, N, wgs):
+    say("mfma vs valu coefficients", L, N, wgs)
+    out = []
+    for path in ("early", "valu"):
+        p = make(gpu_lib, path, L=L, N=N)
+        p.set_schedule(wgs)
+        out.append(p.coefficients([p.from_str(v) for v in BENCH_X0]))
+    for c in range(3):
+        for i, (a, b) in enumerate(zip(out[0][c], out[1][c])):
+            assert a == b, (c, i)
+
+
 @pytest.mark.parametrize("L,N,wgs,steps", [(12, 40, 7, 30), (84, 120, 64, 4), (208, 600, 256, 3),
                                            (416, 400, 256, 2)])
-def test_mfma_and_valu_paths_give_the_same_bits(gpu_lib, L, N, wgs, steps):
-    say("mfma vs valu", L, N, wgs, steps)
+@pytest.mark.parametrize("path", ["early"])
+def test_mfma_and_valu_paths_give_the_same_bits(gpu_lib, L, N, wgs, steps, path):
+    say("mfma vs valu", path, L, N, wgs, steps)
     x0 = None
     out = []
-    for path in ("mfma", "valu"):
+    for path in (path, "valu"):
         p = make(gpu_lib, path, L=L, N=N)
         p.set_schedule(wgs)
         if x0 is None:
@@ -81,10 +99,10 @@ def test_mfma_z_axis_and_spread_error(gpu_lib):
     ctx = lz.make_context(L=12, N=40)
     x0 = (ZERO, ZERO, lz.state_from_strings(ctx, ("0", "0", "35.64"))[2])
     ref = lz.integrate(ctx, x0, 5)
-    p = make(gpu_lib, "mfma", L=12, N=40)
+    p = make(gpu_lib, "early", L=12, N=40)
     p.set_schedule(16)
     assert p.integrate([tuple(v) for v in x0], 5) == [tuple(v) for v in ref]
-    q = make(gpu_lib, "mfma", L=4, N=4)
+    q = make(gpu_lib, "early", L=4, N=4)
     q.set_schedule(9)
     bad = lz.state_from_strings(lz.make_context(L=4, N=4), ("1e-200", "1", "1"))
     with pytest.raises(gpu_lib.MptsError) as ei:
