@@ -134,9 +134,28 @@ int mpts_integrate_dev(mpts_ctx *ctx, const void *x0_dev, int64_t nsteps,
                        size_t ws_bytes, void *stream);
 
 /* Synchronises `stream` and returns the device error status recorded in
- * the workspace by the last call (MPTS_OK or MPTS_ERANGE). */
+ * the workspace by the last call (MPTS_OK or MPTS_ERANGE).  workspace NULL:
+ * the status of the last mpts_integrate_dev_noalloc call on the current
+ * device. */
 int mpts_check(mpts_ctx *ctx, void *workspace, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * integration as mpts_integrate_dev, with the workspace taken from a device
+ * array inside the library (MPTS_NOALLOC_SCRATCH_BYTES bytes, one copy per
+ * GPU, held until the process ends) instead of caller memory.  The call
+ * allocates nothing: it launches the same kernels and copies its small
+ * descriptors into that array on `stream`.  x0_dev, xout_dev and ckpt_dev
+ * (may be NULL) are caller-owned packed device states as for
+ * mpts_integrate_dev.  Sizes whose workspace exceeds the array (the rows of
+ * 3 (N+1) coefficients, about 3 (N+1) (4L + 200) bytes, plus about 0.3 MB)
+ * return MPTS_ENOSPC with the need in mpts_last_error.  Every call on one
+ * GPU shares that GPU's array, which keeps the last call's contents; calls
+ * that overlap on one GPU (other streams, other threads) race and must be
+ * serialised by the caller.  Device errors: mpts_check(ctx, NULL, stream). */
+#define MPTS_NOALLOC_SCRATCH_BYTES (32u << 20)
+int mpts_integrate_dev_noalloc(mpts_ctx *ctx, const void *x0_dev, int64_t nsteps,
+                               void *xout_dev, void *ckpt_dev, void *stream);
 
 /* The Taylor coefficients alpha_i, beta_i, gamma_i, i = 0..N (equation (3))
  * of one step from x0, each N+1 arrays of caller-owned mpts_bf (L limbs). */

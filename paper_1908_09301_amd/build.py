@@ -40,7 +40,7 @@ def build(verbose: bool = False) -> str:
             obj = os.path.join(tmp, f"kernels_cm{cm}.o")
             jobs.append((obj, [hipcc, *FLAGS, *inc, f"-DMPTS_CM={cm}", "-c",
                                os.path.join(CSRC, "mpts_kernels.hip"), "-o", obj]))
-        for src in ("mpts_host.cpp", "mpts_dispatch.cpp", "mpts_probe.hip"):
+        for src in ("mpts_host.cpp", "mpts_dispatch.cpp", "mpts_probe.hip", "mpts_noalloc.hip"):
             obj = os.path.join(tmp, os.path.splitext(src)[0] + ".o")
             jobs.append((obj, [hipcc, *FLAGS, *inc, "-c", os.path.join(CSRC, src), "-o", obj]))
         procs = []

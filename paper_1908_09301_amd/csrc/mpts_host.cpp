@@ -980,6 +980,22 @@ void graph_evict(uint64_t gen) {
 
 }  // namespace
 
+namespace mpts {
+
+int noalloc_scratch(void **ptr);  // mpts_noalloc.hip
+
+int integrate_fits(mpts_ctx *c, int64_t nsteps, size_t limit) {
+  const size_t need = layout(c, nsteps, false, kMaxWG, false).total;
+  if (need <= limit) return MPTS_OK;
+  char msg[160];
+  snprintf(msg, sizeof(msg),
+           "needs %zu bytes of workspace; the library's scratch array holds %zu (L=%d, N=%d)", need,
+           limit, c->L, c->N);
+  return set_err(c, MPTS_ENOSPC, msg);
+}
+
+}  // namespace mpts
+
 
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -1115,7 +1131,13 @@ int mpts_integrate_dev(mpts_ctx *c, const void *x0_dev, int64_t nsteps, void *xo
 }
 
 int mpts_check(mpts_ctx *c, void *ws, void *stream) {
-  if (!c || !ws) return MPTS_EINVAL;
+  if (!c) return MPTS_EINVAL;
+  if (!ws) {
+    // the calls without a workspace record their status in the library's
+    // scratch array of the current device
+    int st = mpts::noalloc_scratch(&ws);
+    if (st != MPTS_OK) return set_err(c, st, "no scratch array on this device");
+  }
   return read_status(c, ws, (hipStream_t)stream);
 }
 

@@ -38,7 +38,7 @@ SYMBOLS = (
     "mpts_integrate", "mpts_integrate_dev", "mpts_check", "mpts_coefficients",
     "mpts_batch_workspace_bytes", "mpts_integrate_batch", "mpts_grad",
     "mpts_grad_batch_workspace_bytes", "mpts_grad_batch", "mpts_release_caches",
-    "mpts_probe_rate", "mpts_strerror", "mpts_last_error",
+    "mpts_probe_rate", "mpts_integrate_dev_noalloc", "mpts_strerror", "mpts_last_error",
 )
 
 if not os.path.exists(LIB_PATH):
@@ -89,6 +89,7 @@ _lib.mpts_grad_batch.argtypes = [ctypes.POINTER(_P), _i32, _BFP, ctypes.POINTER(
                                  _DP, _BFP, _P, _sz, _P]
 _lib.mpts_release_caches.argtypes = []
 _lib.mpts_probe_rate.argtypes = [_i32, _DP, _P, _sz, _P]
+_lib.mpts_integrate_dev_noalloc.argtypes = [_P, _P, _i64, _P, _P, _P]
 _lib.mpts_strerror.argtypes = [_i32]
 _lib.mpts_strerror.restype = ctypes.c_char_p
 _lib.mpts_last_error.argtypes = [_P]
@@ -292,8 +293,19 @@ class Lorenz:
             ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
         return ws
 
+    def integrate_dev_noalloc(self, x0_dev, nsteps: int, xout_dev, ckpt_dev=None):
+        """As integrate_dev with the library's own device scratch array as
+        the workspace (no allocation); errors from the device through
+        check(None)."""
+        self._check(_lib.mpts_integrate_dev_noalloc(
+            self._h, ctypes.c_void_p(x0_dev.data_ptr()), nsteps, ctypes.c_void_p(xout_dev.data_ptr()),
+            ctypes.c_void_p(ckpt_dev.data_ptr()) if ckpt_dev is not None else None, _stream()))
+
     def check(self, ws):
-        self._check(_lib.mpts_check(self._h, ctypes.c_void_p(ws.data_ptr()), _stream()))
+        """Device status of the last call on workspace ws (None: of the last
+        allocation-free call on this device)."""
+        self._check(_lib.mpts_check(self._h, ctypes.c_void_p(ws.data_ptr()) if ws is not None
+                                    else None, _stream()))
 
     def coefficients(self, x0):
         """Taylor coefficients (alpha, beta, gamma), each N+1 values, of one
