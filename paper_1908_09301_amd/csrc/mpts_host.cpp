@@ -374,6 +374,7 @@ struct Layout {
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 constexpr int kMaxWG = 4096;
+constexpr size_t kLdsPerCU = 160 * 1024;  // LDS one gfx950 workgroup can hold
 
 // Workspace of one trajectory.  The parts every call uses come first (the
 // batch takes a region up to `inst` per trajectory); the coefficient output
@@ -423,7 +424,7 @@ int check_device(mpts_ctx *c) {
   if (strncmp(pr.gcnArchName, "gfx950", 6) != 0)
     return set_err(c, MPTS_EARCH, std::string("device is ") + pr.gcnArchName + ", need gfx950");
   c->cus = pr.multiProcessorCount;
-  c->lds = lds_bytes(c->L, c->N, c->RS, c->WB, c->CM, false);
+  c->lds = lds_bytes(c->L, c->N, c->RS, c->WB, c->CM, false, c->mfma != 0);
   int occ = max_coresident(c->CM, c->lds, &c->max_per_cu, false);
   if (occ != 0 || c->max_per_cu < 1) {
     char msg[160];
@@ -481,6 +482,11 @@ int make_ctx(const char *sigma, const char *R, const char *b, int L, int N, cons
   // give the same bits; the matrix cores hold rows of up to 495 digits)
   const char *early = getenv("MPTS_EARLY");
   c->mfma = mf_fits(c->nd) && !(early && strcmp(early, "valu") == 0) ? 1 : 0;
+  // the staging buffers must leave the forward and adjoint kernels within
+  // one compute unit's LDS, else the VALU tiles take the early products
+  if (c->mfma && (lds_bytes(L, N, c->RS, c->WB, c->CM, false, true) > kLdsPerCU ||
+                  lds_bytes(L, N, c->RS, c->WB, c->CM, true, true) > kLdsPerCU))
+    c->mfma = 0;
   c->cn.assign((size_t)NCONST * (L + 2), 0);
   std::vector<int32_t> nv;
   auto put = [&](int idx, const std::vector<int32_t> &v) {
@@ -541,7 +547,7 @@ int run_single(mpts_ctx *c, int mode, long long nsteps, const void *x0_dev, void
   if (dst != MPTS_OK) return dst;
   const bool adj = mode == MODE_ADJOINT;
   if (adj && c->max_per_cu_adj < 0) {
-    c->lds_adj = lds_bytes(c->L, c->N, c->RS, c->WB, c->CM, true);
+    c->lds_adj = lds_bytes(c->L, c->N, c->RS, c->WB, c->CM, true, c->mfma != 0);
     int occ = max_coresident(c->CM, c->lds_adj, &c->max_per_cu_adj, true);
     if (occ != 0) c->max_per_cu_adj = 0;
   }
@@ -720,7 +726,7 @@ int batch_layout(mpts_ctx *const *ctxs, int count, BatchLayout &bl) {
   if (bl.CM < 0) return MPTS_EUNSUPPORTED;
   for (int t = 0; t < count; ++t) {
     mpts_ctx *c = ctxs[t];
-    bl.lds = std::max(bl.lds, lds_bytes(c->L, c->N, c->RS, c->WB, bl.CM, false));
+    bl.lds = std::max(bl.lds, lds_bytes(c->L, c->N, c->RS, c->WB, bl.CM, false, c->mfma != 0));
   }
   return MPTS_OK;
 }
@@ -920,8 +926,8 @@ int grad_batch_layout(mpts_ctx *const *ctxs, int count, const int64_t *nsteps, G
   if (gl.CM < 0) return MPTS_EUNSUPPORTED;
   for (int t = 0; t < count; ++t) {
     mpts_ctx *c = ctxs[t];
-    gl.lds_fwd = std::max(gl.lds_fwd, lds_bytes(c->L, c->N, c->RS, c->WB, gl.CM, false));
-    gl.lds_adj = std::max(gl.lds_adj, lds_bytes(c->L, c->N, c->RS, c->WB, gl.CM, true));
+    gl.lds_fwd = std::max(gl.lds_fwd, lds_bytes(c->L, c->N, c->RS, c->WB, gl.CM, false, c->mfma != 0));
+    gl.lds_adj = std::max(gl.lds_adj, lds_bytes(c->L, c->N, c->RS, c->WB, gl.CM, true, c->mfma != 0));
   }
   return MPTS_OK;
 }
@@ -995,7 +1001,6 @@ int integrate_fits(mpts_ctx *c, int64_t nsteps, size_t limit) {
 }
 
 }  // namespace mpts
-
 
 // ---------------------------------------------------------------------------
 extern "C" {

@@ -23,7 +23,7 @@ MPTS_DECLARE_CM(cm32)
 #undef MPTS_DECLARE_CM
 
 // Bytes of dynamic LDS one workgroup of the forward (or adjoint) kernel needs.
-size_t lds_bytes(int L, int N, int RS, int WB, int CM, bool adjoint);
+size_t lds_bytes(int L, int N, int RS, int WB, int CM, bool adjoint, bool mfma);
 
 // Launch of the persistent forward kernel over `nwg` workgroups; workgroup w
 // runs trajectory d_insts[d_wg_inst[w]].  `cooperative` asks the runtime to

@@ -355,10 +355,10 @@ struct Carve {
 // per-term offset tables alias the task columns (they live from frame setup
 // to the end of the products, the task columns only during finalisation).
 __host__ __device__ inline size_t task_region_bytes(int L, int N, int nd, int RS, int CM,
-                                                   bool adjoint) {
+                                                   bool adjoint, bool mfma) {
   const int NV = (L + 2 + 3) & ~3;
   size_t b = (size_t)3 * 64 * CM * 8 + (size_t)6 * (NV > RS ? NV : RS) * 4 + (size_t)4 * RS * 4;
-  if (mf_fits(nd)) {
+  if (mfma && mf_fits(nd)) {
     const size_t st = (size_t)mf_stage_bytes(nd);
     if (st > b) b = st;
   }
@@ -381,7 +381,8 @@ __device__ Carve carve(unsigned char *smem, const Inst &I) {
   c.trow = (int32_t *)p;
   p += (size_t)6 * (NV > I.RS ? NV : I.RS) * 4;
   c.hrow = (int32_t *)p;
-  p = task0 + task_region_bytes(I.L, I.N, I.nd, I.RS, I.CM, I.mode == MODE_ADJOINT);
+  p = task0 + task_region_bytes(I.L, I.N, I.nd, I.RS, I.CM, I.mode == MODE_ADJOINT,
+                                (I.mfma & 1) != 0);
   c.fs = (FrameSrc *)p;
   p += sizeof(FrameSrc) * (NFR + 2);
   c.fd = (FrameD *)p;
@@ -417,9 +418,9 @@ __device__ __forceinline__ void prof_mark(const Inst &I, const Carve &cv, int ph
 }
 
 #if MPTS_CM == 4
-size_t lds_bytes(int L, int N, int RS, int WB, int CM, bool adjoint) {
+size_t lds_bytes(int L, int N, int RS, int WB, int CM, bool adjoint, bool mfma) {
   const int nd = digits_per_row(L);
-  size_t b = (size_t)NFR * WB * 8 + task_region_bytes(L, N, nd, RS, CM, adjoint) +
+  size_t b = (size_t)NFR * WB * 8 + task_region_bytes(L, N, nd, RS, CM, adjoint, mfma) +
              sizeof(FrameSrc) * (NFR + 2) + sizeof(FrameD) * (NFR + 2) + 96 * 4 +
              8 + 4 * NFR * 4 + ((size_t)3 * (N + 1) + 3 * NCONST) * 4;
   return (b + 255) & ~(size_t)255;
@@ -1041,16 +1042,11 @@ __device__ void late_step(const Inst &I, const Carve &cv, int rank, int i, Group
 // 0 and 1 from their fixed bases (cv.fd[NFR], cv.fd[NFR + 1]).  The terms
 // are dealt to the followers in contiguous ranges; a workgroup stages one
 // term at a time (the next term's digits are loaded while the current one
-// is multiplied) and its wavefronts split the (U block, output tile) pairs.
-// Sets the early column spans of frames 0 and 1.
-__device__ void mfma_early(const Inst &I, const Carve &cv, int rank, int j) {
-  const int tid = threadIdx.x, wave = tid >> 6;
-  const int nd = I.nd;
-  const MfGeo g = mf_geo(nd);
-  const int n = j - 1;
-  const unsigned W = (unsigned)(I.G - 1), r = (unsigned)(rank - 1);
-  const int k0 = 1 + (int)(((unsigned long long)n * r) / W);
-  const int k1 = 1 + (int)(((unsigned long long)n * (r + 1)) / W);
+// is multiplied) and its wavefronts split the U blocks.  Terms k0..k1-1.
+template <int NQX, int JQ>
+__device__ void mfma_terms(const Inst &I, const Carve &cv, int rank, int j, int k0, int k1,
+                           const MfGeo &g) {
+  const int tid = threadIdx.x, nd = I.nd;
   const l_i32 *ha = (const l_i32 *)hc_row(I, cv, 0), *hb = (const l_i32 *)hc_row(I, cv, 1),
               *hg = (const l_i32 *)hc_row(I, cv, 2);
   const int b0 = ((const l_i32 *)&cv.fd[NFR].base)[0], b1 = ((const l_i32 *)&cv.fd[NFR + 1].base)[0];
@@ -1058,13 +1054,6 @@ __device__ void mfma_early(const Inst &I, const Carve &cv, int rank, int j) {
     if (eu == HZ || ev == HZ) return 0;
     return min(max(eu + ev - base, 0), 2 * SMAX);
   };
-  if (tid < 2) {
-    l_i32 *es = (l_i32 *)cv.span + 2 * NFR + 2 * tid;
-    es[0] = 0;
-    es[1] = k1 > k0 ? min(I.WB, 256 * g.NT + 1) : 0;
-  }
-  if (k1 <= k0) return;
-  const MfPairs pr = mf_pairs(g, __builtin_amdgcn_readfirstlane(wave));
   mf_v16i acc[2][MF_NTMAX];
 #pragma unroll
   for (int f = 0; f < 2; ++f)
@@ -1083,6 +1072,7 @@ __device__ void mfma_early(const Inst &I, const Carve &cv, int rank, int j) {
       tq = now;
     }
   };
+  int32_t *P = (int32_t *)(cv.stage + 2 * (size_t)g.BUF);
   MfPrefetch pf;
   mf_load(pf, row_ptr(I, 0, j - k0), row_ptr(I, 2, k0), row_ptr(I, 1, k0), nd);
   int cnt = 0;
@@ -1094,16 +1084,51 @@ __device__ void mfma_early(const Inst &I, const Carve &cv, int rank, int j) {
     __syncthreads();
     mark(13);
     if (k + 1 < k1) mf_load(pf, row_ptr(I, 0, j - k - 1), row_ptr(I, 2, k + 1), row_ptr(I, 1, k + 1), nd);
-    mf_term<2>(acc, buf, g, pr);
+    mf_term<NQX, JQ>(acc, buf, g);
     mark(11);
     if (++cnt == g.FT) {
-      mf_flush<2>(acc, cv.lf, I.WB, g);
+      mf_flush<2>(acc, P, g);
+      __syncthreads();
+      mf_columns(P, cv.lf, I.WB, g);
       cnt = 0;
       mark(12);
     }
   }
-  if (cnt > 0) mf_flush<2>(acc, cv.lf, I.WB, g);
+  if (cnt > 0) {
+    mf_flush<2>(acc, P, g);
+    __syncthreads();
+    mf_columns(P, cv.lf, I.WB, g);
+  }
   mark(12);
+}
+
+// Sets the early column spans of frames 0 and 1, then runs the terms with
+// the operand counts of this row size (every size mf_fits admits is one of
+// the cases below).
+__device__ void mfma_early(const Inst &I, const Carve &cv, int rank, int j, uint32_t *err) {
+  const int tid = threadIdx.x;
+  const MfGeo g = mf_geo(I.nd);
+  const int n = j - 1;
+  const unsigned W = (unsigned)(I.G - 1), r = (unsigned)(rank - 1);
+  const int k0 = 1 + (int)(((unsigned long long)n * r) / W);
+  const int k1 = 1 + (int)(((unsigned long long)n * (r + 1)) / W);
+  if (tid < 2) {
+    l_i32 *es = (l_i32 *)cv.span + 2 * NFR + 2 * tid;
+    es[0] = 0;
+    es[1] = k1 > k0 ? min(I.WB, 256 * g.NT + 1) : 0;
+  }
+  if (k1 <= k0) return;
+  const int key = g.NQX * 8 + g.JQ;
+  switch (key) {
+    case 1 * 8 + 0: mfma_terms<1, 0>(I, cv, rank, j, k0, k1, g); break;
+    case 2 * 8 + 0: mfma_terms<2, 0>(I, cv, rank, j, k0, k1, g); break;
+    case 3 * 8 + 0: mfma_terms<3, 0>(I, cv, rank, j, k0, k1, g); break;
+    case 3 * 8 + 2: mfma_terms<3, 2>(I, cv, rank, j, k0, k1, g); break;
+    case 3 * 8 + 3: mfma_terms<3, 3>(I, cv, rank, j, k0, k1, g); break;
+    case 4 * 8 + 3: mfma_terms<4, 3>(I, cv, rank, j, k0, k1, g); break;
+    default:
+      if (tid == 0) atomicOr(err, 8u);  // a size mf_fits should have refused
+  }
 }
 
 // The Taylor coefficients 1..N of one step (equation (3)), rows 0 given.
@@ -1274,7 +1299,7 @@ __device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, G
       unsigned long long *tp = I.prof && rank == 1 ? I.prof + PH_NPHASE + 9 : nullptr;
       unsigned long long *tmx = (unsigned long long *)(cv.red + 32);
       if (I.mfma & 1)
-        mfma_early(I, cv, rank, j);
+        mfma_early(I, cv, rank, j, err);
       else
         frames_accumulate(cv.fs + NFR, cv.fd + NFR, 2, nd, RS, I.WB, cv.lf, rank, I.G,
                           cv.span + 2 * NFR, true, tp, tmx);

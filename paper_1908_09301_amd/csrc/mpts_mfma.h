@@ -20,10 +20,15 @@
 // on the output side); the i32 accumulators are flushed into the frame's
 // 64-bit columns (28-bit weights) before they can overflow.
 //
+// X depends on R - m only, so the blocks m = r and m = r + 32 use the same
+// X operands (output tiles q and q + 1): a wavefront takes a range of r and
+// for each loads two W operands and one X operand per tile and frame, which
+// halves the LDS reads per product against one block at a time.
+//
 // One workgroup takes a contiguous range of terms of the two Cauchy frames
 // of an index (they share U_k = a_{i-k}); for each term it stages the three
-// rows as pieces in LDS, and its four wavefronts split the (m, output tile)
-// pairs, each holding the accumulators of both frames for its pairs.
+// rows as pieces in LDS, and its four wavefronts split the blocks r, each
+// holding the accumulators of both frames for every output tile.
 #pragma once
 #include <hip/hip_runtime.h>
 #include "mpts_common.h"
@@ -33,26 +38,35 @@ namespace mpts {
 
 typedef __attribute__((address_space(3))) uint8_t l_u8;
 typedef __attribute__((address_space(3))) uint32_t l_u32;
+typedef __attribute__((address_space(3), aligned(1))) uint32_t l_u32u;
 typedef int mf_v16i __attribute__((ext_vector_type(16)));
+typedef int mf_v4i __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3), aligned(4))) mf_v4i l_v4i4;
+typedef __attribute__((address_space(3))) mf_v4i l_v4i16;
 
 constexpr int MF_OFFP = 4 * 2 * SMAX;  // largest term offset in pieces
 constexpr int MF_VLO = 1120;           // V pieces below 0 that a read can reach (35 blocks)
 constexpr int MF_NTMAX = 4;            // output tiles of 1024 pieces held per wavefront
+constexpr int MF_VB = 48;              // bytes per 32-piece V block (16-byte aligned reads)
 
-// Piece geometry for rows of nd digits.  The U row is stored reversed
-// (piece x at byte ZU - x); a V row in blocks of 32 pieces at a stride of 36
-// bytes (so that the 32 lanes of a read, one block each, hit 32 different
-// LDS banks), logical piece P at block (P + MF_VLO) / 32.
+// Piece geometry for rows of nd digits.  The U row is stored reversed (piece
+// x at byte ZU - x) in four copies, copy c shifted up by c bytes, so that
+// every lane's 16-byte W window starts on a 4-byte boundary of one copy; a
+// V row in blocks of 32 pieces at a stride of MF_VB bytes, logical piece P
+// at block (P + MF_VLO) / 32.
 struct MfGeo {
   int NP;   // pieces per row
   int MM;   // U blocks m = 0..MM-1 that can hold a piece
   int NT;   // output tiles (1024 pieces each) that can hold a nonzero sum
-  int DQH;  // largest 32 q - m whose V blocks can hold a piece
-  int ZU;   // byte of U piece 0 in its buffer (ZU = 3 mod 4)
-  int UBs;  // bytes of the U buffer
-  int VBLK; // 36-byte blocks of a V buffer
+  int DQH;  // last V block that can hold a piece
+  int NQX;  // X operands (tiles) per block r: X(32 q - r), q < NQX
+  int JQ;   // tiles q + 1 of the block r + 32 that exist (0: no block r + 32)
+  int RR;   // blocks r = 0..RR-1 (r and r + 32)
+  int ZU;   // byte of U piece 0 in a copy (ZU = 3 mod 4)
+  int UCS;  // bytes of one U copy
+  int VBLK; // blocks of a V buffer
   int VBs;  // bytes of a V buffer
-  int BUF;  // bytes of one staging buffer: U, V0, V1
+  int BUF;  // bytes of one staging buffer: four U copies, V0, V1
   int FT;   // terms between flushes of the i32 accumulators
 };
 
@@ -62,12 +76,16 @@ __host__ __device__ inline MfGeo mf_geo(int nd) {
   g.MM = (g.NP + 30) / 32 + 1;
   g.NT = (2 * g.NP + MF_OFFP) / 1024 + 1;
   g.DQH = (g.NP + MF_OFFP - 1) / 32;
-  g.ZU = 4 * ((g.NP + 61 + 3) / 4) + 3;
-  g.UBs = (g.ZU + 32 + 15) & ~15;
+  const int nq = (31 + g.DQH) / 32 + 1;
+  g.NQX = nq < g.NT ? nq : g.NT;
+  g.JQ = g.MM > 32 ? (g.NQX < g.NT - 1 ? g.NQX : g.NT - 1) : 0;
+  g.RR = g.MM < 32 ? g.MM : 32;
+  g.ZU = 4 * ((g.NP + 64) / 4) + 3;
+  g.UCS = (g.ZU + 64 + 15) & ~15;
   // logical pieces [-MF_VLO, NP + MF_OFFP + 1056) in 32-piece blocks
   g.VBLK = (MF_VLO + g.NP + MF_OFFP + 1056 + 31) / 32;
-  g.VBs = (36 * g.VBLK + 15) & ~15;
-  g.BUF = g.UBs + 2 * g.VBs;
+  g.VBs = (MF_VB * g.VBLK + 15) & ~15;
+  g.BUF = 4 * g.UCS + 2 * g.VBs;
   // one term adds at most NP products of magnitude <= 127^2 to an output
   const long long per_term = (long long)g.NP * 127 * 127;
   long long ft = per_term > 0 ? 2147483647LL / per_term : 1;
@@ -75,12 +93,22 @@ __host__ __device__ inline MfGeo mf_geo(int nd) {
   return g;
 }
 
-// Staging bytes (two buffers) the MFMA path needs in LDS.
-__host__ __device__ inline int mf_stage_bytes(int nd) { return 2 * mf_geo(nd).BUF; }
+// Piece sums of one index, both frames: int32 P[f][pi], pi = 32 R + t <
+// 1024 NT, after the two staging buffers.
+__host__ __device__ inline int mf_parr_bytes(const MfGeo &g) { return 2 * g.NT * 1024 * 4; }
 
-// Whether the MFMA path holds this size (all output tiles in one wavefront's
-// accumulators).
-__host__ __device__ inline bool mf_fits(int nd) { return mf_geo(nd).NT <= MF_NTMAX; }
+// Staging bytes (two buffers and the piece sums) the MFMA path needs in LDS.
+__host__ __device__ inline int mf_stage_bytes(int nd) {
+  const MfGeo g = mf_geo(nd);
+  return 2 * g.BUF + mf_parr_bytes(g);
+}
+
+// Whether the MFMA path holds this size (all output tiles in one
+// wavefront's accumulators, U blocks r and r + 32 only).
+__host__ __device__ inline bool mf_fits(int nd) {
+  const MfGeo g = mf_geo(nd);
+  return g.NT <= MF_NTMAX && g.MM <= 64;
+}
 
 // The four pieces s p0..s p3 of a 28-bit digit D, packed little-endian
 // (forward = true: p0 in the low byte) or reversed (p3 in the low byte).
@@ -96,24 +124,24 @@ __device__ __forceinline__ uint32_t mf_pieces(int32_t D, bool forward) {
                  : (p[3] | (p[2] << 8) | (p[1] << 16) | (p[0] << 24));
 }
 
-// Byte address in a V buffer of logical piece P (a multiple of 4 or the
-// start of an 8-byte read at s0 + 8h within a block).
+// Byte address in a V buffer of logical piece P.
 __device__ __forceinline__ int mf_vaddr(int P) {
   const int b = P + MF_VLO;
-  return 36 * (b >> 5) + (b & 31);
+  return MF_VB * (b >> 5) + (b & 31);
 }
 
-// Zero both staging buffers (every thread of the workgroup).
+// Zero both staging buffers and the piece sums (every thread of the
+// workgroup).
 __device__ __forceinline__ void mf_clear(uint8_t *stage, const MfGeo &g) {
   l_u32 *p = (l_u32 *)stage;
-  for (int w = threadIdx.x; w < (2 * g.BUF) / 4; w += WGS) p[w] = 0u;
+  for (int w = threadIdx.x; w < (2 * g.BUF + mf_parr_bytes(g)) / 4; w += WGS) p[w] = 0u;
 }
 
 // Digits of one term's three rows, loaded by every thread (thread tid holds
 // digits tid, tid + WGS, ... of each row; MF_PF per row at most).
 constexpr int MF_PF = 3;  // nd <= 3 * WGS = 768 digits
 struct MfPrefetch {
-  int32_t u[MF_PF], v0[MF_PF], v1[MF_PF];
+  int32_t u[MF_PF], un[MF_PF], v0[MF_PF], v1[MF_PF];  // un: the U digit above u
 };
 
 // (buffer loads: digits past nd read 0 without touching memory)
@@ -126,24 +154,41 @@ __device__ __forceinline__ void mf_load(MfPrefetch &r, const int32_t *U, const i
   for (int j = 0; j < MF_PF; ++j) {
     const int o = 4 * (threadIdx.x + j * WGS);
     r.u[j] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(ru, o, 0, 0);
+    r.un[j] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(ru, o + 4, 0, 0);
     r.v0[j] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(ra, o, 0, 0);
     r.v1[j] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rb, o, 0, 0);
   }
 }
 
-// Store a prefetched term into staging buffer `buf`: U reversed, V0 and V1
-// shifted up by their offsets (in digits; each V write also clears the
-// pieces up to NP + MF_OFFP so that no piece of an earlier term with a
-// larger offset survives).
+// Store a prefetched term into staging buffer `buf`: U reversed into its
+// four copies, V0 and V1 shifted up by their offsets (in digits; each V
+// write also clears the pieces up to NP + MF_OFFP so that no piece of an
+// earlier term with a larger offset survives).
+//
+// Copy c holds piece x at byte ZU - x + c, so its aligned word at ZU - 3 - 4 D
+// holds the pieces 4 D + c .. 4 D + c + 3: the reversed pieces of digit D
+// shifted up by c bytes, below them the top c reversed pieces of digit D + 1
+// (words D = -1 .. nd-1).  The U pieces of every term occupy the same
+// bytes, so the copies' padding stays zero.
 __device__ __forceinline__ void mf_store(const MfPrefetch &r, uint8_t *buf, const MfGeo &g, int nd,
                                          int off0, int off1) {
   l_u8 *U = (l_u8 *)buf;
-  l_u8 *V0 = U + g.UBs, *V1 = V0 + g.VBs;
+  l_u8 *V0 = U + 4 * g.UCS, *V1 = V0 + g.VBs;
   const int ndw = nd + 2 * SMAX;  // digit slots of a shifted V row
 #pragma unroll
   for (int j = 0; j < MF_PF; ++j) {
     const int d = threadIdx.x + j * WGS;
-    if (d < nd) *(l_u32 *)(U + g.ZU - 4 * d - 3) = mf_pieces(r.u[j], false);
+    if (d < nd) {
+      const uint32_t w = mf_pieces(r.u[j], false), wn = mf_pieces(r.un[j], false);
+      l_u8 *a = U + g.ZU - 3 - 4 * d;
+      *(l_u32 *)a = w;
+#pragma unroll
+      for (int c = 1; c < 4; ++c) *(l_u32 *)(a + c * g.UCS) = (w << (8 * c)) | (wn >> (32 - 8 * c));
+      if (d == 0) {
+#pragma unroll
+        for (int c = 1; c < 4; ++c) *(l_u32 *)(a + 4 + c * g.UCS) = w >> (32 - 8 * c);
+      }
+    }
   }
   // V slots s = 0..ndw-1 hold digit s - off (zero outside the row)
 #pragma unroll
@@ -162,185 +207,95 @@ __device__ __forceinline__ void mf_store(const MfPrefetch &r, uint8_t *buf, cons
   }
 }
 
-// 8 bytes from LDS at any byte address (gfx950 reads unaligned LDS words
-// in one ds_read_b64).
-typedef __attribute__((address_space(3), aligned(1))) uint64_t l_u64u;
-// 8 bytes from LDS at any byte address (gfx950 reads unaligned LDS words
-// in one ds_read_b64).
-typedef __attribute__((address_space(3), aligned(1))) uint64_t l_u64u;
-// Stage a digit row held in LDS (header, RPAD zero digits, nd digits) as
-// pieces: reversed into a U buffer, or at offset 0 into a V buffer (whose
-// other slots must already be zero).  Every thread of the workgroup.
-__device__ __forceinline__ void mf_stage_lds_row(const int32_t *row_, uint8_t *dst, bool as_u,
-                                                 const MfGeo &g, int nd) {
-  const l_i32 *row = (const l_i32 *)row_ + HDR + RPAD;
-  l_u8 *D = (l_u8 *)dst;
-  for (int d = threadIdx.x; d < nd; d += WGS) {
-    const int32_t v = row[d];
-    if (as_u) *(l_u32 *)(D + g.ZU - 4 * d - 3) = mf_pieces(v, false);
-    else *(l_u32 *)(D + mf_vaddr(4 * d)) = mf_pieces(v, true);
-  }
-}
-
-__device__ __forceinline__ uint64_t mf_ld64(const l_u8 *p) { return *(const l_u64u *)p; }
-
-// The (m, tile) pairs of this wavefront: pairs in (m, q) order, q valid for
-// m when 32 q - m lies in [-31, DQH] (a contiguous range of q for each m);
-// wavefront w takes pairs [P w / 4, P (w+1) / 4).  All of it is uniform over
-// the wavefront (scalar registers): `wave` comes through readfirstlane.
-struct MfPairs {
-  int m0, m1;    // first and last U block with pairs of this wavefront (m0 > m1: none)
-  int qa0, qb1;  // first tile of block m0 and last tile of block m1 that are its pairs
-};
-
-__device__ __forceinline__ void mf_qrange(const MfGeo &g, int m, int *qlo, int *qhi) {
-  // 32 q - m >= -31  <=>  q >= ceil((m - 31) / 32);  32 q - m <= DQH  <=>  q <= (m + DQH) / 32
-  int lo = m >= 31 ? (m - 31 + 31) / 32 : 0;
-  int hi = (m + g.DQH) / 32;
-  if (hi > g.NT - 1) hi = g.NT - 1;
-  *qlo = lo;
-  *qhi = hi;
-}
-
-__device__ __forceinline__ MfPairs mf_pairs(const MfGeo &g, int wave) {
-  int P = 0;
-  for (int m = 0; m < g.MM; ++m) {
-    int lo, hi;
-    mf_qrange(g, m, &lo, &hi);
-    P += hi >= lo ? hi - lo + 1 : 0;
-  }
-  const int plo = P * wave / 4, phi = P * (wave + 1) / 4;
-  MfPairs r;
-  r.m0 = 0;
-  r.m1 = -1;
-  r.qa0 = r.qb1 = 0;
-  int pi = 0;
-  for (int m = 0; m < g.MM; ++m) {
-    int lo, hi;
-    mf_qrange(g, m, &lo, &hi);
-    for (int q = lo; q <= hi; ++q, ++pi) {
-      if (pi == plo) {
-        r.m0 = m;
-        r.qa0 = q;
-      }
-      if (pi == phi - 1) {
-        r.m1 = m;
-        r.qb1 = q;
-      }
-    }
-  }
-  if (phi <= plo) r.m1 = -1;
-  return r;
-}
-
-// One term on this wavefront's pairs: acc[f][q] += W (U's Toeplitz blocks)
-// times X (V_f's blocks) for f < NF, one v_mfma_i32_32x32x32_i8 each:
-// lane l (t = l % 32, h = l / 32) supplies the inner indices s = 16 h + u,
-// u = 0..15, of both operands (the instruction sums over s, so any fixed
-// assignment of s to the lane's bytes that both operands share is exact):
+// The operands of one block r: W of U blocks r and r + 32, and X(32 q - r)
+// of both frames for q < NQX.  Lane l (t = l % 32, h = l / 32) supplies the
+// inner indices s = 16 h + u, u = 0..15, of both operands (the instruction
+// sums over s, so any fixed assignment of s to the lane's bytes that both
+// operands share is exact):
 //   W bytes u: U[32 m + t - 16 h - u], 16 consecutive bytes of the reversed
-//              U buffer from ZU - 32 m - t + 16 h;
-//   X bytes u: V[32 (32 q + t - m) + 16 h + u], 16 bytes of block
-//              32 q + t - m from offset 16 h.
-// The operands of U block m + 1 are loaded while the products of block m
-// are issued (two register stages).
-typedef int mf_v4i __attribute__((ext_vector_type(4)));
-typedef __attribute__((address_space(3), aligned(1))) mf_v4i l_v4iu1;
-typedef __attribute__((address_space(3), aligned(4))) mf_v4i l_v4iu4;
-// 16 bytes at any byte address (the W reads) or at a multiple of 4 (X)
-__device__ __forceinline__ mf_v4i mf_ld128(const l_u8 *p) { return *(const l_v4iu1 *)p; }
-__device__ __forceinline__ mf_v4i mf_ld128a4(const l_u8 *p) { return *(const l_v4iu4 *)p; }
-
-template <int NF>
-struct MfStage {
-  mf_v4i w;
-  mf_v4i x[NF][MF_NTMAX];
-  int qlo, qhi;
+//              U from ZU - 32 m - t + 16 h, read from the copy c = (t + 1) % 4
+//              whose shift makes that address a multiple of 4;
+//   X bytes u: V[32 (32 q + t - r) + 16 h + u], 16 bytes of block
+//              32 q + t - r from offset 16 h (16-byte aligned).
+// Blocks past the V buffer read its last block, which holds no piece; tiles
+// whose blocks hold no piece multiply zeros.
+template <int NQX>
+struct MfOps {
+  mf_v4i w0, w1;
+  mf_v4i x[2][NQX];
 };
 
-template <int NF>
-__device__ __forceinline__ void mf_stage_load(MfStage<NF> &st, const l_u8 *wbase, const l_u8 *V0,
-                                              const l_u8 *V1, int xl, int m, int qlo, int qhi) {
-  st.qlo = qlo;
-  st.qhi = qhi;
-  st.w = mf_ld128(wbase - 32 * m);
-  // every tile's operands are loaded (tiles outside [qlo, qhi] from tile
-  // qlo's address, and not used), so that the number of LDS reads in flight
-  // is fixed and the waits before the products can be exact
+template <int NQX>
+__device__ __forceinline__ void mf_ops_load(MfOps<NQX> &o, const l_u8 *wb, const l_u8 *V0,
+                                            const l_u8 *V1, int xt, const MfGeo &g, int r, bool j1) {
+  o.w0 = *(const l_v4i4 *)(wb - 32 * r);
+  o.w1 = *(const l_v4i4 *)(wb - 32 * (j1 ? r + 32 : r));
 #pragma unroll
-  for (int q = 0; q < MF_NTMAX; ++q) {
-    const int qq = q < qlo ? qlo : q > qhi ? qlo : q;
-    const int xo = xl + 36 * (32 * qq - m);
-    st.x[0][q] = mf_ld128a4(V0 + xo);
-    if constexpr (NF > 1) st.x[1][q] = mf_ld128a4(V1 + xo);
+  for (int q = 0; q < NQX; ++q) {
+    int b = 32 * q - r + xt;
+    b = b < g.VBLK - 1 ? b : g.VBLK - 1;
+    o.x[0][q] = *(const l_v4i16 *)(V0 + MF_VB * b);
+    o.x[1][q] = *(const l_v4i16 *)(V1 + MF_VB * b);
   }
 }
 
-template <int NF>
-__device__ __forceinline__ void mf_stage_mma(mf_v16i (&acc)[NF][MF_NTMAX], const MfStage<NF> &st) {
+// The products of block r: tiles q (U block r) and q + 1 (U block r + 32).
+template <int NQX, int JQ>
+__device__ __forceinline__ void mf_ops_mma(mf_v16i (&acc)[2][MF_NTMAX], const MfOps<NQX> &o,
+                                           bool j1) {
 #pragma unroll
-  for (int q = 0; q < MF_NTMAX; ++q) {
-    if (q < st.qlo || q > st.qhi) continue;
+  for (int q = 0; q < NQX; ++q)
 #pragma unroll
-    for (int f = 0; f < NF; ++f)
-      acc[f][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(st.x[f][q], st.w, acc[f][q], 0, 0, 0);
+    for (int f = 0; f < 2; ++f)
+      acc[f][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.x[f][q], o.w0, acc[f][q], 0, 0, 0);
+  if (JQ > 0 && j1) {
+#pragma unroll
+    for (int q = 0; q < JQ; ++q)
+#pragma unroll
+      for (int f = 0; f < 2; ++f)
+        acc[f][q + 1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.x[f][q], o.w1, acc[f][q + 1], 0, 0, 0);
   }
 }
 
-// Tiles of block m among this wavefront's pairs.
-__device__ __forceinline__ void mf_qclip(const MfGeo &g, const MfPairs &pr, int m, int *qlo,
-                                         int *qhi) {
-  mf_qrange(g, m, qlo, qhi);
-  if (m == pr.m0) *qlo = pr.qa0;
-  if (m == pr.m1) *qhi = pr.qb1;
+// One term on this wavefront's blocks r (a range of [0, RR) per wavefront):
+// acc[f][q] += the output tile q of frame f.  The operands of block r + 1
+// are loaded while the products of block r are issued (two register
+// stages; the last block is loaded again at the end, so that the number of
+// reads in flight is fixed).
+template <int NQX, int JQ>
+__device__ __forceinline__ void mf_term(mf_v16i (&acc)[2][MF_NTMAX], const uint8_t *buf,
+                                        const MfGeo &g) {
+  const int lane = threadIdx.x & 63, t = lane & 31, h = lane >> 5, c = (t + 1) & 3;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r0 = g.RR * wave / 4, r1 = g.RR * (wave + 1) / 4;
+  if (r0 >= r1) return;
+  const l_u8 *wb = (const l_u8 *)buf + c * g.UCS + c + g.ZU - t + 16 * h;
+  const l_u8 *V0 = (const l_u8 *)buf + 4 * g.UCS + 16 * h, *V1 = V0 + g.VBs;
+  const int xt = t + MF_VLO / 32;
+  MfOps<NQX> A, B;
+  mf_ops_load<NQX>(A, wb, V0, V1, xt, g, r0, r0 + 32 < g.MM);
+  for (int r = r0;; r += 2) {
+    const int rb = r + 1 < r1 ? r + 1 : r1 - 1;
+    mf_ops_load<NQX>(B, wb, V0, V1, xt, g, rb, rb + 32 < g.MM);
+    mf_ops_mma<NQX, JQ>(acc, A, r + 32 < g.MM);
+    if (r + 1 >= r1) break;
+    const int ra = r + 2 < r1 ? r + 2 : r1 - 1;
+    mf_ops_load<NQX>(A, wb, V0, V1, xt, g, ra, ra + 32 < g.MM);
+    mf_ops_mma<NQX, JQ>(acc, B, r + 33 < g.MM);
+    if (r + 2 >= r1) break;
+  }
 }
 
+// Add the accumulators into the piece sums P and clear them.  The products
+// are issued as X^T W^T (the transpose of O = W X), so lane l holds
+// position t = l % 32 of the blocks R = 32 q + 8 b + 4 (l / 32) + r in its
+// registers 4 b + r: output position pi = 32 R + t.  One LDS add per
+// register and lane, 64 distinct positions per instruction (the wavefronts
+// of the workgroup add into the same sums).
 template <int NF>
-__device__ __forceinline__ void mf_term(mf_v16i (&acc)[NF][MF_NTMAX], const uint8_t *buf,
-                                        const MfGeo &g, const MfPairs &pr) {
+__device__ __forceinline__ void mf_flush(mf_v16i (&acc)[NF][MF_NTMAX], int32_t *P, const MfGeo &g) {
   const int lane = threadIdx.x & 63, t = lane & 31, h = lane >> 5;
-  const l_u8 *U = (const l_u8 *)buf;
-  const l_u8 *V0 = U + g.UBs, *V1 = V0 + g.VBs;
-  // per-lane parts of the addresses
-  const l_u8 *wbase = U + g.ZU - t + 16 * h;
-  const int xl = 36 * (t + MF_VLO / 32) + 16 * h;
-  const int m0 = __builtin_amdgcn_readfirstlane(pr.m0), m1 = __builtin_amdgcn_readfirstlane(pr.m1);
-  if (m0 > m1) return;
-  // two register stages in turn: the operands of the next block are loaded
-  // (unconditionally, the last block again at the end, so that the number of
-  // reads in flight is fixed) while the current block's products issue
-  MfStage<NF> A, B;
-  int qa, qb;
-  mf_qclip(g, pr, m0, &qa, &qb);
-  mf_stage_load<NF>(A, wbase, V0, V1, xl, m0, qa, qb);
-  for (int m = m0;; m += 2) {
-    const int mb = m + 1 < m1 ? m + 1 : m1;
-    mf_qclip(g, pr, mb, &qa, &qb);
-    mf_stage_load<NF>(B, wbase, V0, V1, xl, mb, qa, qb);
-    mf_stage_mma<NF>(acc, A);
-    if (m + 1 > m1) break;
-    const int ma = m + 2 < m1 ? m + 2 : m1;
-    mf_qclip(g, pr, ma, &qa, &qb);
-    mf_stage_load<NF>(A, wbase, V0, V1, xl, ma, qa, qb);
-    mf_stage_mma<NF>(acc, B);
-    if (m + 2 > m1) break;
-  }
-}
-
-// Add the accumulators into the frames' 64-bit LDS columns lf[f * WB + c]
-// and clear them.  The products are issued as X^T W^T (the transpose of
-// O = W X), so lane l holds position t = l % 32 of the blocks
-// R = 32 q + 8 b + 4 (l / 32) + r in its registers 4 b + r: output position
-// pi = 32 R + t, column pi / 4 with weight 2^(7 (pi % 4)).  The four lanes
-// t = 4c'..4c'+3 hold the four pieces of one column: they are weighted and
-// added across the lane group (DPP row shifts), and the group's last lane
-// adds the column into LDS, so each atomic instruction touches 16 columns
-// in runs of 8 consecutive ones.
-template <int NF>
-__device__ __forceinline__ void mf_flush(mf_v16i (&acc)[NF][MF_NTMAX], long long *lf, int WB,
-                                         const MfGeo &g) {
-  const int lane = threadIdx.x & 63, t = lane & 31, h = lane >> 5;
-  const int sh = 7 * (t & 3);
+  l_i32 *lp = (l_i32 *)P;
 #pragma unroll
   for (int f = 0; f < NF; ++f)
 #pragma unroll
@@ -348,20 +303,35 @@ __device__ __forceinline__ void mf_flush(mf_v16i (&acc)[NF][MF_NTMAX], long long
       if (q < g.NT) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          long long v = (long long)acc[f][q][r] * (long long)(1 << sh);
-          v = dpp_sum4_64(v);
           const int R = 32 * q + 8 * (r >> 2) + 4 * h + (r & 3);
-          const int c = 8 * R + (t >> 2);
-          if ((t & 3) == 3 && v != 0 && c < WB)
-            __hip_atomic_fetch_add((unsigned long long __attribute__((address_space(3))) *)
-                                       ((l_i64 *)lf + (size_t)f * WB + c),
-                                   (unsigned long long)v, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+          __hip_atomic_fetch_add(lp + f * g.NT * 1024 + 32 * R + t, acc[f][q][r], __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
         }
       }
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[f][q][r] = 0;
     }
+}
+
+// Move the piece sums into the frames' 64-bit LDS columns lf[f * WB + c]
+// (column c = pi / 4 with weight 2^(7 (pi % 4))) and clear them; every
+// thread of the workgroup, after every wavefront's mf_flush.
+__device__ __forceinline__ void mf_columns(int32_t *P, long long *lf, int WB, const MfGeo &g) {
+  const int ncol = g.NT * 256;
+  for (int w = threadIdx.x; w < 2 * ncol; w += WGS) {
+    const int f = w >= ncol ? 1 : 0, c = w - f * ncol;
+    l_v4i16 *pp = (l_v4i16 *)((l_i32 *)P + f * g.NT * 1024 + 4 * c);
+    const mf_v4i v = *pp;
+    if ((v.x | v.y | v.z | v.w) != 0) {
+      const long long s = (long long)v.x + (long long)v.y * 128LL + (long long)v.z * 16384LL +
+                          (long long)v.w * 2097152LL;
+      if (c < WB)
+        __hip_atomic_fetch_add((unsigned long long __attribute__((address_space(3))) *)
+                                   ((l_i64 *)lf + (size_t)f * WB + c),
+                               (unsigned long long)s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      *pp = mf_v4i{0, 0, 0, 0};
+    }
+  }
 }
 
 }  // namespace mpts
