@@ -55,7 +55,7 @@ extern "C" {
  * than this from the first term of its sum makes the call fail with
  * MPTS_ERANGE (some schedules still hold a somewhat wider spread exactly);
  * a result is never inexact. */
-#define MPTS_MAX_SPREAD_BITS 448
+#define MPTS_MAX_SPREAD_BITS 672
 
 /* flags for mpts_integrate / mpts_integrate_batch */
 #define MPTS_CHECKPOINTS 1u    /* keep every per-step state (see checkpoints) */

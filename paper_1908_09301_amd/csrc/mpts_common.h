@@ -18,9 +18,9 @@ constexpr int DBITS = 28;                      // bits per product digit
 constexpr long long DMASK = (1LL << DBITS) - 1;
 constexpr int TQ = 8;                          // tile edge in digits (8x8 products per lane)
 constexpr int WGS = 256;                       // threads per workgroup
-constexpr int SMAX = 16;                       // largest exponent spread (digits) of one exact sum
+constexpr int SMAX = 24;                       // largest exponent spread (digits) of one exact sum
 constexpr int HDR = 8;                         // row header words
-constexpr int RPAD = 40;                       // zero digits on each side of a row
+constexpr int RPAD = 2 * SMAX + 8;             // zero digits on each side of a row (every term offset)
 constexpr int NFR = 5;                         // product frames per coefficient index
 constexpr int FLUSH_TERMS = 15;                // terms between accumulator carry-normalisations
 

@@ -121,7 +121,7 @@ def test_spread_beyond_window_is_reported(gpu_lib, wgs):
     p = gpu_lib.Lorenz(L=4, N=4)
     p.set_schedule(wgs)
     ctx = lz.make_context(L=4, N=4)
-    x0 = lz.state_from_strings(ctx, ("1e-200", "1", "1"))
+    x0 = lz.state_from_strings(ctx, ("1e-300", "1", "1"))
     with pytest.raises(gpu_lib.MptsError) as ei:
         p.integrate([T(v) for v in x0], 1)
     assert ei.value.code == gpu_lib.MPTS_ERANGE

@@ -104,7 +104,7 @@ def test_mfma_z_axis_and_spread_error(gpu_lib):
     assert p.integrate([tuple(v) for v in x0], 5) == [tuple(v) for v in ref]
     q = make(gpu_lib, "early", L=4, N=4)
     q.set_schedule(9)
-    bad = lz.state_from_strings(lz.make_context(L=4, N=4), ("1e-200", "1", "1"))
+    bad = lz.state_from_strings(lz.make_context(L=4, N=4), ("1e-300", "1", "1"))
     with pytest.raises(gpu_lib.MptsError) as ei:
         q.integrate([tuple(v) for v in bad], 1)
     assert ei.value.code == gpu_lib.MPTS_ERANGE
