@@ -375,6 +375,7 @@ size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 constexpr int kMaxWG = 4096;
 constexpr size_t kLdsPerCU = 160 * 1024;  // LDS one gfx950 workgroup can hold
+constexpr int kMfmaMinDigits = 320;       // rows from which the matrix cores take the early products
 
 // Workspace of one trajectory.  The parts every call uses come first (the
 // batch takes a region up to `inst` per trajectory); the coefficient output
@@ -478,10 +479,15 @@ int make_ctx(const char *sigma, const char *R, const char *b, int L, int N, cons
     delete c;
     return MPTS_EUNSUPPORTED;
   }
-  // MPTS_EARLY=valu keeps the early products on the VALU tiles (both paths
-  // give the same bits; the matrix cores hold rows of up to 495 digits)
+  // Early products on the matrix cores for rows of at least kMfmaMinDigits
+  // digits (below that the VALU tiles are faster) that the accumulators
+  // hold (at most 487 digits); MPTS_EARLY=valu or =mfma overrides the size
+  // rule (both paths give the same bits)
   const char *early = getenv("MPTS_EARLY");
-  c->mfma = mf_fits(c->nd) && !(early && strcmp(early, "valu") == 0) ? 1 : 0;
+  bool use = c->nd >= kMfmaMinDigits;
+  if (early && strcmp(early, "valu") == 0) use = false;
+  if (early && strcmp(early, "mfma") == 0) use = true;
+  c->mfma = use && mf_fits(c->nd) ? 1 : 0;
   // the staging buffers must leave the forward and adjoint kernels within
   // one compute unit's LDS, else the VALU tiles take the early products
   if (c->mfma && (lds_bytes(L, N, c->RS, c->WB, c->CM, false, true) > kLdsPerCU ||

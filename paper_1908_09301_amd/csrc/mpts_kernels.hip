@@ -596,7 +596,7 @@ __device__ void group_publish(const Inst &I, bool leader, GroupSync &gs, uint32_
 // of the products into LDS, and (G > 1) the L2-bypassing atomic adds of
 // its columns into the group's global frames.  The leader then waits for
 // every workgroup's adds.  Returns the frames the leader finalises from.
-__device__ const long long *group_bulk(const Inst &I, const Carve &cv, int nf, int rank,
+__device__ __forceinline__ const long long *group_bulk(const Inst &I, const Carve &cv, int nf, int rank,
                                        GroupSync &gs, uint32_t *err) {
   const int tid = threadIdx.x;
   const int G = I.G, WB = I.WB;
@@ -1043,7 +1043,7 @@ __device__ void late_step(const Inst &I, const Carve &cv, int rank, int i, Group
 // are dealt to the followers in contiguous ranges; a workgroup stages one
 // term at a time (the next term's digits are loaded while the current one
 // is multiplied) and its wavefronts split the U blocks.  Terms k0..k1-1.
-template <int NQX, int JQ>
+template <int NQA, int JQA, int NQB, int JQB>
 __device__ void mfma_terms(const Inst &I, const Carve &cv, int rank, int j, int k0, int k1,
                            const MfGeo &g) {
   const int tid = threadIdx.x, nd = I.nd;
@@ -1084,7 +1084,7 @@ __device__ void mfma_terms(const Inst &I, const Carve &cv, int rank, int j, int 
     __syncthreads();
     mark(13);
     if (k + 1 < k1) mf_load(pf, row_ptr(I, 0, j - k - 1), row_ptr(I, 2, k + 1), row_ptr(I, 1, k + 1), nd);
-    mf_term<NQX, JQ>(acc, buf, g);
+    mf_term<NQA, JQA, NQB, JQB>(acc, buf, g);
     mark(11);
     if (++cnt == g.FT) {
       mf_flush<2>(acc, P, g);
@@ -1105,7 +1105,7 @@ __device__ void mfma_terms(const Inst &I, const Carve &cv, int rank, int j, int 
 // Sets the early column spans of frames 0 and 1, then runs the terms with
 // the operand counts of this row size (every size mf_fits admits is one of
 // the cases below).
-__device__ void mfma_early(const Inst &I, const Carve &cv, int rank, int j, uint32_t *err) {
+__device__ __forceinline__ void mfma_early(const Inst &I, const Carve &cv, int rank, int j, uint32_t *err) {
   const int tid = threadIdx.x;
   const MfGeo g = mf_geo(I.nd);
   const int n = j - 1;
@@ -1118,14 +1118,21 @@ __device__ void mfma_early(const Inst &I, const Carve &cv, int rank, int j, uint
     es[1] = k1 > k0 ? min(I.WB, 256 * g.NT + 1) : 0;
   }
   if (k1 <= k0) return;
-  const int key = g.NQX * 8 + g.JQ;
+  const int key = ((g.NQA * 8 + g.JQA) * 8 + g.NQB) * 8 + g.JQB;
   switch (key) {
-    case 1 * 8 + 0: mfma_terms<1, 0>(I, cv, rank, j, k0, k1, g); break;
-    case 2 * 8 + 0: mfma_terms<2, 0>(I, cv, rank, j, k0, k1, g); break;
-    case 3 * 8 + 0: mfma_terms<3, 0>(I, cv, rank, j, k0, k1, g); break;
-    case 3 * 8 + 2: mfma_terms<3, 2>(I, cv, rank, j, k0, k1, g); break;
-    case 3 * 8 + 3: mfma_terms<3, 3>(I, cv, rank, j, k0, k1, g); break;
-    case 4 * 8 + 3: mfma_terms<4, 3>(I, cv, rank, j, k0, k1, g); break;
+#define MF_CASE(a, b, c, d)                                        \
+  case ((a * 8 + b) * 8 + c) * 8 + d:                              \
+    mfma_terms<a, b, c, d>(I, cv, rank, j, k0, k1, g);             \
+    break;
+    MF_CASE(1, 0, 1, 0)
+    MF_CASE(1, 0, 2, 0)
+    MF_CASE(2, 0, 2, 0)
+    MF_CASE(2, 0, 3, 0)
+    MF_CASE(2, 2, 3, 2)
+    MF_CASE(2, 2, 3, 3)
+    MF_CASE(3, 3, 3, 3)
+    MF_CASE(3, 3, 4, 3)
+#undef MF_CASE
     default:
       if (tid == 0) atomicOr(err, 8u);  // a size mf_fits should have refused
   }

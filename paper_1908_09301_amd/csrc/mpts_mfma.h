@@ -59,9 +59,11 @@ struct MfGeo {
   int MM;   // U blocks m = 0..MM-1 that can hold a piece
   int NT;   // output tiles (1024 pieces each) that can hold a nonzero sum
   int DQH;  // last V block that can hold a piece
-  int NQX;  // X operands (tiles) per block r: X(32 q - r), q < NQX
-  int JQ;   // tiles q + 1 of the block r + 32 that exist (0: no block r + 32)
   int RR;   // blocks r = 0..RR-1 (r and r + 32)
+  // X operands X(32 q - r), q < NQ(r), that can hold a piece, and the tiles
+  // q + 1 < JQ(r) + 1 of the block r + 32: (NQA, JQA) for r < RS, (NQB, JQB)
+  // from RS on (NQ(r) grows by at most one over the 32 blocks r)
+  int NQA, JQA, NQB, JQB, RS;
   int ZU;   // byte of U piece 0 in a copy (ZU = 3 mod 4)
   int UCS;  // bytes of one U copy
   int VBLK; // blocks of a V buffer
@@ -76,10 +78,18 @@ __host__ __device__ inline MfGeo mf_geo(int nd) {
   g.MM = (g.NP + 30) / 32 + 1;
   g.NT = (2 * g.NP + MF_OFFP) / 1024 + 1;
   g.DQH = (g.NP + MF_OFFP - 1) / 32;
-  const int nq = (31 + g.DQH) / 32 + 1;
-  g.NQX = nq < g.NT ? nq : g.NT;
-  g.JQ = g.MM > 32 ? (g.NQX < g.NT - 1 ? g.NQX : g.NT - 1) : 0;
   g.RR = g.MM < 32 ? g.MM : 32;
+  auto nq = [&](int r) { const int q = (r + g.DQH) / 32 + 1; return q < g.NT ? q : g.NT; };
+  auto jq = [&](int q) { return g.MM > 32 ? (q < g.NT - 1 ? q : g.NT - 1) : 0; };
+  g.NQA = nq(0);
+  g.NQB = nq(g.RR - 1);
+  g.JQA = jq(g.NQA);
+  g.JQB = jq(g.NQB);
+  // first r with NQ(r) = NQB: 32 NQA - DQH (tiles q < NQ(r) are those with
+  // 32 q - r <= DQH)
+  g.RS = g.NQB > g.NQA ? 32 * g.NQA - g.DQH : g.RR;
+  if (g.RS < 0) g.RS = 0;
+  if (g.RS > g.RR) g.RS = g.RR;
   g.ZU = 4 * ((g.NP + 64) / 4) + 3;
   g.UCS = (g.ZU + 64 + 15) & ~15;
   // logical pieces [-MF_VLO, NP + MF_OFFP + 1056) in 32-piece blocks
@@ -257,18 +267,15 @@ __device__ __forceinline__ void mf_ops_mma(mf_v16i (&acc)[2][MF_NTMAX], const Mf
   }
 }
 
-// One term on this wavefront's blocks r (a range of [0, RR) per wavefront):
+// The blocks r in [r0, r1) of one term, with NQX X operands per frame:
 // acc[f][q] += the output tile q of frame f.  The operands of block r + 1
 // are loaded while the products of block r are issued (two register
 // stages; the last block is loaded again at the end, so that the number of
 // reads in flight is fixed).
 template <int NQX, int JQ>
-__device__ __forceinline__ void mf_term(mf_v16i (&acc)[2][MF_NTMAX], const uint8_t *buf,
-                                        const MfGeo &g) {
+__device__ __forceinline__ void mf_term_range(mf_v16i (&acc)[2][MF_NTMAX], const uint8_t *buf,
+                                              const MfGeo &g, int r0, int r1) {
   const int lane = threadIdx.x & 63, t = lane & 31, h = lane >> 5, c = (t + 1) & 3;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int r0 = g.RR * wave / 4, r1 = g.RR * (wave + 1) / 4;
-  if (r0 >= r1) return;
   const l_u8 *wb = (const l_u8 *)buf + c * g.UCS + c + g.ZU - t + 16 * h;
   const l_u8 *V0 = (const l_u8 *)buf + 4 * g.UCS + 16 * h, *V1 = V0 + g.VBs;
   const int xt = t + MF_VLO / 32;
@@ -284,6 +291,18 @@ __device__ __forceinline__ void mf_term(mf_v16i (&acc)[2][MF_NTMAX], const uint8
     mf_ops_mma<NQX, JQ>(acc, B, r + 33 < g.MM);
     if (r + 2 >= r1) break;
   }
+}
+
+// One term on this wavefront's blocks r (a quarter of [0, RR)), each block
+// with only the X operands that can hold a piece.
+template <int NQA, int JQA, int NQB, int JQB>
+__device__ __forceinline__ void mf_term(mf_v16i (&acc)[2][MF_NTMAX], const uint8_t *buf,
+                                        const MfGeo &g) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r0 = g.RR * wave / 4, r1 = g.RR * (wave + 1) / 4;
+  const int ra = r1 < g.RS ? r1 : g.RS, rb = r0 > g.RS ? r0 : g.RS;
+  if (r0 < ra) mf_term_range<NQA, JQA>(acc, buf, g, r0, ra);
+  if (NQB != NQA && rb < r1) mf_term_range<NQB, JQB>(acc, buf, g, rb, r1);
 }
 
 // Add the accumulators into the piece sums P and clear them.  The products

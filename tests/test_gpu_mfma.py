@@ -2,10 +2,10 @@
 blocks, i32 accumulators flushed into 64-bit columns) against the oracle and
 against the VALU tile path, bit for bit (GPU).
 
-MPTS_EARLY=valu, read when a context is created, selects the VALU tiles;
-by default a context whose rows fit the matrix-core accumulators (at most
-495 digits, L <= 432 limbs) uses the matrix cores whenever its trajectory
-runs on two or more workgroups."""
+MPTS_EARLY=valu or =mfma, read when a context is created, selects the
+path; by default a context whose rows have at least 300 digits and fit the
+matrix-core accumulators (at most 487 digits, L <= 425 limbs) uses the
+matrix cores whenever its trajectory runs on two or more workgroups."""
 import os
 import sys
 
@@ -30,8 +30,7 @@ def make(gpu_lib, path, **kw):
     try:
         for k in keys:
             os.environ.pop(k, None)
-        if path == "valu":
-            os.environ["MPTS_EARLY"] = "valu"
+        os.environ["MPTS_EARLY"] = "valu" if path == "valu" else "mfma"
         return gpu_lib.Lorenz(**kw)
     finally:
         for k, v in old.items():
@@ -42,11 +41,11 @@ def make(gpu_lib, path, **kw):
 
 
 # (L, N, workgroups): one output tile (L <= 84), two, three and four tiles
-# (L = 208, 416, 432: the largest size the accumulators hold), one follower
+# (L = 208, 416, 425: the largest size the accumulators hold), one follower
 # doing every term (G = 2: several accumulator flushes per index at L = 416),
 # odd and XCD-sized groups
 CASES = [(1, 9, 3), (4, 30, 7), (12, 40, 24), (22, 60, 16), (42, 70, 5), (84, 60, 33),
-         (168, 50, 64), (208, 40, 256), (416, 30, 256), (432, 20, 100), (416, 150, 2)]
+         (168, 50, 64), (208, 40, 256), (416, 30, 256), (425, 20, 100), (416, 150, 2)]
 
 
 @pytest.mark.parametrize("L,N,wgs", CASES)
@@ -63,7 +62,7 @@ def test_mfma_coefficients_match_oracle(gpu_lib, L, N, wgs):
             assert tuple(r) == q, (name, i)
 
 
-@pytest.mark.parametrize("L,N,wgs", [(416, 400, 256), (432, 300, 64)])
+@pytest.mark.parametrize("L,N,wgs", [(416, 400, 256), (425, 300, 64)])
 def test_mfma_and_valu_coefficients_agree(gpu_lib, L, N, wgs):
     say("mfma vs valu coefficients", L, N, wgs)
     out = []
