@@ -67,7 +67,7 @@ struct Inst {
   int mode;
   int loss;           // adjoint seed: 0 = 2 x(T) (squared norm), 1..3 = unit vector e_x, e_y, e_z
   int mfma;           // bit 0: early Cauchy products on the int8 matrix cores (else VALU tiles)
-  int pad1;
+  int next;           // batch: 1 + index of the instance the same workgroups run next (0: none)
   long long nsteps;
   int32_t *rows;      // [3][N+1][RS]
   int32_t *consts;    // [NCONST][RS]

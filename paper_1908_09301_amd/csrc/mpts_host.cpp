@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <atomic>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <cmath>
 #include <cstdint>
@@ -864,43 +865,131 @@ int autotune_class(mpts_ctx *c, void *ws, size_t ws_bytes, hipStream_t s, int gm
 // Workgroups per trajectory: start with one each and repeatedly double the
 // group of the trajectory with the longest predicted run while the launch
 // still fits on the device at once.
+// A batch schedule: slots of G workgroups, each running a list of
+// trajectories one after another.
+struct BatchPlan {
+  std::vector<int> slot_G;                 // workgroups of each slot
+  std::vector<std::vector<int>> slot_list; // trajectories of each slot, in order
+  int total = 0;                           // workgroups of the launch
+};
+
+// Plans the batch: trajectories with the same (L, N, nsteps) form a class;
+// for a makespan T each class takes, over the group sizes G of the tuning
+// table, the fewest workgroups that finish it within T (m = floor(T / t(G))
+// trajectories one after another per slot of G workgroups); the smallest T
+// whose classes fit the resident workgroups is found by bisection.  Step
+// times come from the tuner (MPTS_AUTOTUNE) or the model.
 int plan_batch(mpts_ctx *const *ctxs, int count, const int64_t *nsteps, const BatchLayout &bl,
-               bool autotune, void *ws, size_t ws_bytes, hipStream_t s, std::vector<int> &G) {
+               bool autotune, void *ws, size_t ws_bytes, hipStream_t s, BatchPlan &plan) {
   mpts_ctx *c0 = ctxs[0];
   int per_cu = 0;
   if (max_coresident(bl.CM, bl.lds, &per_cu, false) != 0 || per_cu < 1)
     return set_err(c0, MPTS_EUNSUPPORTED, "kernel does not fit one compute unit");
   const int cap = std::min(c0->cus * per_cu, kMaxWG);
-  if (count > cap) return set_err(c0, MPTS_EUNSUPPORTED, "more trajectories than resident workgroups");
   std::lock_guard<std::mutex> lk(g_cache_mu);
   tune_load();
   const std::string arch = device_arch();
-  // a trajectory never takes more than an equal share of the resident
-  // workgroups beyond its first (nor more than the largest tuned group)
-  const int gmax = std::max(1, std::min(kTuneG[kTuneN - 1], cap - count + 1));
+  const int gmax = std::max(1, std::min(kTuneG[kTuneN - 1], cap));
   if (autotune)
     for (int t = 0; t < count; ++t) {
       int st = autotune_class(ctxs[t], ws, ws_bytes, s, gmax, arch);
       if (st) return st;
     }
-  G.assign((size_t)count, 1);
-  int used = count;
-  for (;;) {
-    int worst = -1;
-    double tw = -1.0;
-    for (int t = 0; t < count; ++t) {
-      double tt = nsteps[t] * step_ms(ctxs[t], G[t], arch);
-      if (tt > tw) {
-        tw = tt;
-        worst = t;
+  // classes
+  struct Cls {
+    std::vector<int> members;
+    double cost[kTuneN];  // ms of the whole run on kTuneG[k] workgroups (1e30: not a candidate)
+    int G = 1, m = 1, slots = 0;
+  };
+  std::vector<Cls> cls;
+  std::map<std::tuple<int, int, int64_t>, int> idx;
+  for (int t = 0; t < count; ++t) {
+    const auto key = std::make_tuple(ctxs[t]->L, ctxs[t]->N, (int64_t)nsteps[t]);
+    auto it = idx.find(key);
+    if (it == idx.end()) {
+      Cls c;
+      for (int k = 0; k < kTuneN; ++k)
+        c.cost[k] = kTuneG[k] <= gmax ? std::max(1, (int)nsteps[t]) * step_ms(ctxs[t], kTuneG[k], arch)
+                                      : 1e30;
+      it = idx.emplace(key, (int)cls.size()).first;
+      cls.push_back(c);
+    }
+    cls[it->second].members.push_back(t);
+  }
+  // workgroups class c needs to finish within T (and its choice), or -1
+  auto need = [&](Cls &c, double T, bool keep) -> long long {
+    long long best = -1;
+    for (int k = 0; k < kTuneN; ++k) {
+      if (c.cost[k] >= 1e29 || c.cost[k] > T) continue;
+      const long long n = (long long)c.members.size();
+      long long m = (long long)(T / c.cost[k]);
+      if (m < 1) continue;
+      if (m > n) m = n;
+      const long long slots = (n + m - 1) / m, w = slots * kTuneG[k];
+      if (best < 0 || w < best) {
+        best = w;
+        if (keep) {
+          c.G = kTuneG[k];
+          c.m = (int)m;
+          c.slots = (int)slots;
+        }
       }
     }
-    if (worst < 0 || G[worst] >= gmax) break;
-    int ng = G[worst] * 2;
-    if (used + (ng - G[worst]) > cap) break;
-    if (step_ms(ctxs[worst], ng, arch) >= step_ms(ctxs[worst], G[worst], arch)) break;
-    used += ng - G[worst];
-    G[worst] = ng;
+    return best;
+  };
+  auto feasible = [&](double T, bool keep) {
+    long long used = 0;
+    for (auto &c : cls) {
+      const long long w = need(c, T, keep);
+      if (w < 0) return false;
+      used += w;
+    }
+    return used <= cap;
+  };
+  double hi = 0.0, lo = 0.0;
+  for (auto &c : cls) {
+    double best = 1e30;
+    for (int k = 0; k < kTuneN; ++k) best = std::min(best, c.cost[k]);
+    lo = std::max(lo, best);
+    hi += best * (double)c.members.size();
+  }
+  plan = BatchPlan();
+  if (!feasible(hi, false)) {
+    // more classes than workgroups: one workgroup per slot, trajectories
+    // dealt to the least loaded slot (largest first)
+    const int nslot = std::min(cap, count);
+    std::vector<double> load((size_t)nslot, 0.0);
+    std::vector<int> order((size_t)count);
+    for (int t = 0; t < count; ++t) order[t] = t;
+    auto tcost = [&](int t) { return (double)std::max<int64_t>(1, nsteps[t]) * step_ms(ctxs[t], 1, arch); };
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return tcost(x) > tcost(y); });
+    plan.slot_G.assign((size_t)nslot, 1);
+    plan.slot_list.assign((size_t)nslot, {});
+    for (int t : order) {
+      const int sl = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[sl] += tcost(t);
+      plan.slot_list[sl].push_back(t);
+    }
+    plan.total = nslot;
+    return MPTS_OK;
+  }
+  lo = std::min(lo, hi);
+  for (int it = 0; it < 60 && hi - lo > 1e-6 * hi; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (feasible(mid, false)) hi = mid;
+    else lo = mid;
+  }
+  (void)feasible(hi, true);
+  for (auto &c : cls) {
+    const int base = (int)plan.slot_G.size();
+    for (int k = 0; k < c.slots; ++k) {
+      plan.slot_G.push_back(c.G);
+      plan.slot_list.push_back({});
+    }
+    // round robin: the slots of a class differ by at most one trajectory
+    for (size_t k = 0; k < c.members.size(); ++k)
+      plan.slot_list[base + (int)(k % (size_t)c.slots)].push_back(c.members[k]);
+    plan.total += c.slots * c.G;
   }
   return MPTS_OK;
 }
@@ -953,6 +1042,7 @@ struct GraphKey {
   std::vector<int> LN;  // L, N per trajectory
   std::vector<int64_t> nsteps;
   std::vector<int> G;
+  std::vector<int> sched;  // first workgroup and successor of each trajectory
   bool operator<(const GraphKey &o) const {
     if (ws != o.ws) return ws < o.ws;
     if (device != o.device) return device < o.device;
@@ -961,7 +1051,8 @@ struct GraphKey {
     if (gens != o.gens) return gens < o.gens;
     if (LN != o.LN) return LN < o.LN;
     if (nsteps != o.nsteps) return nsteps < o.nsteps;
-    return G < o.G;
+    if (G != o.G) return G < o.G;
+    return sched < o.sched;
   }
 };
 std::map<GraphKey, hipGraphExec_t> g_graphs;
@@ -1248,16 +1339,43 @@ int mpts_integrate_batch(mpts_ctx *const *ctxs, int32_t count, const mpts_bf *x0
   if (ws_bytes < bl.total) return set_err(c0, MPTS_ENOSPC, "workspace too small");
   char *base = (char *)ws;
   // schedule: workgroups per trajectory
-  std::vector<int> G;
-  st = plan_batch(ctxs, count, nsteps, bl, (flags & MPTS_AUTOTUNE) != 0, ws, ws_bytes, s, G);
+  BatchPlan plan;
+  st = plan_batch(ctxs, count, nsteps, bl, (flags & MPTS_AUTOTUNE) != 0, ws, ws_bytes, s, plan);
   if (st) return st;
-  int total = 0;
-  for (int g : G) total += g;
+  const int total = plan.total;
+  // per trajectory: its slot's workgroups, first workgroup and successor
+  std::vector<int> G((size_t)count, 1), wg0((size_t)count, 0), nxt((size_t)count, 0);
+  std::vector<int> wgmap((size_t)total, -1);
+  {
+    int w = 0;
+    for (size_t sl = 0; sl < plan.slot_G.size(); ++sl) {
+      const auto &lst = plan.slot_list[sl];
+      for (size_t k = 0; k < lst.size(); ++k) {
+        G[lst[k]] = plan.slot_G[sl];
+        wg0[lst[k]] = w;
+        nxt[lst[k]] = k + 1 < lst.size() ? lst[k + 1] + 1 : 0;
+      }
+      for (int j = 0; j < plan.slot_G[sl]; ++j) wgmap[w + j] = lst.empty() ? -1 : lst[0];
+      w += plan.slot_G[sl];
+    }
+  }
+  if (getenv("MPTS_PLAN")) {
+    // the schedule: workgroups per trajectory, by (L, N)
+    std::map<std::pair<int, int>, std::map<int, int>> by;
+    for (int t = 0; t < count; ++t) by[{ctxs[t]->L, ctxs[t]->N}][G[t]]++;
+    int per_cu = 0;
+    (void)max_coresident(bl.CM, bl.lds, &per_cu, false);
+    fprintf(stderr, "mpts plan: %d trajectories, %zu slots, %d workgroups, CM %d, LDS %zu, %d per CU\n",
+            count, plan.slot_G.size(), total, bl.CM, bl.lds, per_cu);
+    for (auto &kv : by) {
+      fprintf(stderr, "  L=%d N=%d:", kv.first.first, kv.first.second);
+      for (auto &g : kv.second) fprintf(stderr, " G%d x%d", g.first, g.second);
+      fprintf(stderr, "\n");
+    }
+  }
   // descriptors, workgroup map, packed states
   std::vector<Inst> insts((size_t)count);
-  std::vector<int> wgmap((size_t)total);
   std::vector<int32_t> states(bl.states_words, 0);
-  int wg = 0;
   for (int t = 0; t < count; ++t) {
     mpts_ctx *c = ctxs[t];
     st = mpts_pack_state(c, x0 + 3 * t, states.data() + bl.state_off[t]);
@@ -1273,7 +1391,8 @@ int mpts_integrate_batch(mpts_ctx *const *ctxs, int32_t count, const mpts_bf *x0
     I.WB = c->WB;
     I.CM = bl.CM;
     I.G = G[t];
-    I.wg0 = wg;
+    I.wg0 = wg0[t];
+    I.next = nxt[t];
     I.mode = MODE_INTEGRATE;
     I.mfma = c->mfma;
     I.nsteps = nsteps[t];
@@ -1283,8 +1402,6 @@ int mpts_integrate_batch(mpts_ctx *const *ctxs, int32_t count, const mpts_bf *x0
     I.state = (int32_t *)(base + bl.states) + bl.state_off[t];
     I.gframes = (long long *)(rb + l.gframes);
     I.sync = (uint32_t *)(rb + l.sync);
-    for (int j = 0; j < G[t]; ++j) wgmap[wg + j] = t;
-    wg += G[t];
     hipError_t e = hipMemcpyAsync(rb + l.cnorm, c->cn.data(), c->cn.size() * 4,
                                   hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_err(c0, e, "copy constants");
@@ -1326,6 +1443,10 @@ int mpts_integrate_batch(mpts_ctx *const *ctxs, int32_t count, const mpts_bf *x0
     }
     key.nsteps.assign(nsteps, nsteps + count);
     key.G = G;
+    for (int t = 0; t < count; ++t) {
+      key.sched.push_back(wg0[t]);
+      key.sched.push_back(nxt[t]);
+    }
     std::lock_guard<std::mutex> lk(g_cache_mu);
     hipGraphExec_t exec = graph_lookup(key);
     if (!exec) {

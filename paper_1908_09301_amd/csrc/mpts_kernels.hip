@@ -1388,11 +1388,9 @@ __device__ __noinline__ void tau_chains(const Inst &I, const Carve &cv, int coun
 }
 
 template <int CM>
-__global__ void __launch_bounds__(WGS) k_run(const Inst *__restrict__ insts,
-                                             const int *__restrict__ wg_inst) {
+__device__ __forceinline__ void run_instance(const Inst &I) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const Inst I = insts[wg_inst[blockIdx.x]];
   const int rank = blockIdx.x - I.wg0, G = I.G;
   const bool leader = rank == 0;
   const int L = I.L, N = I.N, nd = I.nd, RS = I.RS, WB = I.WB;
@@ -1481,6 +1479,20 @@ __global__ void __launch_bounds__(WGS) k_run(const Inst *__restrict__ insts,
       __syncthreads();
       prof_mark(I, cv, PH_HORNER);
     }
+  }
+}
+
+// Every workgroup runs the instance wg_inst[blockIdx.x], then the ones
+// chained after it on the same workgroups (a batch may run several
+// trajectories one after another on one group).
+template <int CM>
+__global__ void __launch_bounds__(WGS) k_run(const Inst *__restrict__ insts,
+                                             const int *__restrict__ wg_inst) {
+  for (int q = wg_inst[blockIdx.x]; q >= 0;) {
+    const Inst I = insts[q];
+    run_instance<CM>(I);
+    q = I.next - 1;
+    __syncthreads();
   }
 }
 
