@@ -946,7 +946,8 @@ __device__ FrameD late_desc(const Inst &I, const Carve &cv, int f, int i, uint32
 // LDS frames, then the columns it holds (with the early products of frames
 // 0 and 1 of this index, accumulated there before) added into the group's
 // frames in global memory, then its arrival.
-__device__ void late_step(const Inst &I, const Carve &cv, int rank, int i, GroupSync &gs) {
+__device__ __forceinline__ void late_step(const Inst &I, const Carve &cv, int rank, int i,
+                                          GroupSync &gs) {
   const int tid = threadIdx.x, WB = I.WB;
   const l_i32 *g = (const l_i32 *)cv.geo;
   l_i32 *span = (l_i32 *)cv.span;
@@ -1045,7 +1046,7 @@ __device__ void late_step(const Inst &I, const Carve &cv, int rank, int i, Group
 // is multiplied) and its wavefronts split the U blocks.  Terms k0..k1-1.
 template <int NQA, int JQA, int NQB, int JQB>
 __device__ void mfma_terms(const Inst &I, const Carve &cv, int rank, int j, int k0, int k1,
-                           const MfGeo &g) {
+                           const MfGeo &g, const MfPrefetch *first) {
   const int tid = threadIdx.x, nd = I.nd;
   const l_i32 *ha = (const l_i32 *)hc_row(I, cv, 0), *hb = (const l_i32 *)hc_row(I, cv, 1),
               *hg = (const l_i32 *)hc_row(I, cv, 2);
@@ -1074,7 +1075,8 @@ __device__ void mfma_terms(const Inst &I, const Carve &cv, int rank, int j, int 
   };
   int32_t *P = (int32_t *)(cv.stage + 2 * (size_t)g.BUF);
   MfPrefetch pf;
-  mf_load(pf, row_ptr(I, 0, j - k0), row_ptr(I, 2, k0), row_ptr(I, 1, k0), nd);
+  if (first) pf = *first;
+  else mf_load(pf, row_ptr(I, 0, j - k0), row_ptr(I, 2, k0), row_ptr(I, 1, k0), nd);
   int cnt = 0;
   for (int k = k0; k < k1; ++k) {
     uint8_t *buf = cv.stage + (size_t)((k - k0) & 1) * g.BUF;
@@ -1105,7 +1107,8 @@ __device__ void mfma_terms(const Inst &I, const Carve &cv, int rank, int j, int 
 // Sets the early column spans of frames 0 and 1, then runs the terms with
 // the operand counts of this row size (every size mf_fits admits is one of
 // the cases below).
-__device__ __forceinline__ void mfma_early(const Inst &I, const Carve &cv, int rank, int j, uint32_t *err) {
+__device__ __forceinline__ void mfma_early(const Inst &I, const Carve &cv, int rank, int j, uint32_t *err,
+                                           const MfPrefetch *first) {
   const int tid = threadIdx.x;
   const MfGeo g = mf_geo(I.nd);
   const int n = j - 1;
@@ -1122,7 +1125,7 @@ __device__ __forceinline__ void mfma_early(const Inst &I, const Carve &cv, int r
   switch (key) {
 #define MF_CASE(a, b, c, d)                                        \
   case ((a * 8 + b) * 8 + c) * 8 + d:                              \
-    mfma_terms<a, b, c, d>(I, cv, rank, j, k0, k1, g);             \
+    mfma_terms<a, b, c, d>(I, cv, rank, j, k0, k1, g, first);      \
     break;
     MF_CASE(1, 0, 1, 0)
     MF_CASE(1, 0, 2, 0)
@@ -1263,6 +1266,20 @@ __device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, G
     return;
   }
   for (int i = 0; i < I.N; ++i) {
+    // the digits of this follower's first early term of index i+1 (rows
+    // <= i, already published) load while the late products of i run
+    MfPrefetch pre;
+    bool have_pre = false;
+    if ((I.mfma & 1) && i + 1 < I.N && i + 1 >= 2) {
+      const int n = i;
+      const unsigned W = (unsigned)(I.G - 1), r = (unsigned)(rank - 1);
+      const int k0 = 1 + (int)(((unsigned long long)n * r) / W);
+      const int k1 = 1 + (int)(((unsigned long long)n * (r + 1)) / W);
+      if (k1 > k0) {
+        mf_load(pre, row_ptr(I, 0, i + 1 - k0), row_ptr(I, 2, k0), row_ptr(I, 1, k0), nd);
+        have_pre = true;
+      }
+    }
     late_step(I, cv, rank, i, gs);
     if (i + 1 < I.N && i + 1 >= 2) {
       // early part of index j = i+1: Cauchy terms k = 1..j-1 (rows <= i).
@@ -1291,12 +1308,20 @@ __device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, G
       prof_mark(I, cv, PH_EBUILD);
       {
         // every term must lie in its frame's window (else the sum is not
-        // exact: reported through the error word, no barrier needed)
+        // exact: reported through the error word, no barrier needed); on
+        // the matrix cores each follower checks the terms it multiplies
+        // (contiguous ranges that cover 1..j-1), else every term is checked
         const int b0 = cv.fd[NFR].base, b1 = cv.fd[NFR + 1].base;
         const l_i32 *la = (const l_i32 *)ha, *lg = (const l_i32 *)hg, *lb = (const l_i32 *)hb;
-        for (int t = tid; t < 2 * (j - 1); t += WGS) {
-          const int f = t >= j - 1 ? 1 : 0;
-          const int k = t - f * (j - 1) + 1;
+        int ka = 1, kn = j - 1;
+        if (I.mfma & 1) {
+          const unsigned W = (unsigned)(I.G - 1), r = (unsigned)(rank - 1);
+          ka = 1 + (int)(((unsigned long long)(j - 1) * r) / W);
+          kn = 1 + (int)(((unsigned long long)(j - 1) * (r + 1)) / W) - ka;
+        }
+        for (int t = tid; t < 2 * kn; t += WGS) {
+          const int f = t >= kn ? 1 : 0;
+          const int k = t - f * kn + ka;
           const int e = esum2(la[j - k], f == 0 ? lg[k] : lb[k]);
           const int base = f == 0 ? b0 : b1;
           if (e != HZ && (e < base || e > base + 2 * SMAX)) atomicOr(err, 1u | 16u);
@@ -1306,7 +1331,7 @@ __device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, G
       unsigned long long *tp = I.prof && rank == 1 ? I.prof + PH_NPHASE + 9 : nullptr;
       unsigned long long *tmx = (unsigned long long *)(cv.red + 32);
       if (I.mfma & 1)
-        mfma_early(I, cv, rank, j, err);
+        mfma_early(I, cv, rank, j, err, have_pre ? &pre : nullptr);
       else
         frames_accumulate(cv.fs + NFR, cv.fd + NFR, 2, nd, RS, I.WB, cv.lf, rank, I.G,
                           cv.span + 2 * NFR, true, tp, tmx);
