@@ -91,7 +91,10 @@ __host__ __device__ inline MfGeo mf_geo(int nd) {
   if (g.RS < 0) g.RS = 0;
   if (g.RS > g.RR) g.RS = g.RR;
   g.ZU = 4 * ((g.NP + 64) / 4) + 3;
+  // copies 64 bytes apart modulo 256 (16 LDS banks): the lanes of a W read
+  // that take different copies then reach different banks
   g.UCS = (g.ZU + 64 + 15) & ~15;
+  g.UCS += (64 - (g.UCS & 255) + 256) & 255;
   // logical pieces [-MF_VLO, NP + MF_OFFP + 1056) in 32-piece blocks
   g.VBLK = (MF_VLO + g.NP + MF_OFFP + 1056 + 31) / 32;
   g.VBs = (MF_VB * g.VBLK + 15) & ~15;
