@@ -120,21 +120,19 @@ __host__ __device__ inline int mf_stage_bytes(int nd) {
 // wavefront's accumulators, U blocks r and r + 32 only).
 __host__ __device__ inline bool mf_fits(int nd) {
   const MfGeo g = mf_geo(nd);
-  return g.NT <= MF_NTMAX && g.MM <= 64;
+  return g.NT <= MF_NTMAX && g.MM <= 64 && nd <= 2 * WGS;
 }
 
 // The four pieces s p0..s p3 of a 28-bit digit D, packed little-endian
 // (forward = true: p0 in the low byte) or reversed (p3 in the low byte).
 __device__ __forceinline__ uint32_t mf_pieces(int32_t D, bool forward) {
   const uint32_t M = (uint32_t)(D < 0 ? -D : D);
-  uint32_t p[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int v = (int)((M >> (7 * q)) & 127u);
-    p[q] = (uint32_t)(uint8_t)(int8_t)(D < 0 ? -v : v);
-  }
-  return forward ? (p[0] | (p[1] << 8) | (p[2] << 16) | (p[3] << 24))
-                 : (p[3] | (p[2] << 8) | (p[1] << 16) | (p[0] << 24));
+  // 7-bit fields of |D| spread one per byte (p0 in the low byte)
+  uint32_t w = (M & 0x7fu) | ((M << 1) & 0x7f00u) | ((M << 2) & 0x7f0000u) | ((M << 3) & 0x7f000000u);
+  // negative digit: every byte v becomes (256 - v) mod 256; bytes are at most
+  // 127, so 128 - v per byte needs no borrow across bytes
+  if (D < 0) w = (0x80808080u - w) ^ 0x80808080u;
+  return forward ? w : __builtin_bswap32(w);
 }
 
 // Byte address in a V buffer of logical piece P.
@@ -152,7 +150,7 @@ __device__ __forceinline__ void mf_clear(uint8_t *stage, const MfGeo &g) {
 
 // Digits of one term's three rows, loaded by every thread (thread tid holds
 // digits tid, tid + WGS, ... of each row; MF_PF per row at most).
-constexpr int MF_PF = 3;  // nd <= 3 * WGS = 768 digits
+constexpr int MF_PF = 2;  // nd <= 2 * WGS = 512 digits (mf_fits admits at most 487)
 struct MfPrefetch {
   int32_t u[MF_PF], un[MF_PF], v0[MF_PF], v1[MF_PF];  // un: the U digit above u
 };
@@ -208,9 +206,12 @@ __device__ __forceinline__ void mf_store(const MfPrefetch &r, uint8_t *buf, cons
   for (int f = 0; f < 2; ++f) {
     l_u8 *V = f ? V1 : V0;
     const int off = f ? off1 : off0;
-    // clear the slots below the shifted row and above it up to ndw
-    for (int s = threadIdx.x; s < ndw; s += WGS) {
-      if (s < off || s >= off + nd) *(l_u32 *)(V + mf_vaddr(4 * s)) = 0u;
+    // clear the slots below the shifted row ([0, off)) and above it up to
+    // ndw ([off + nd, ndw)): at most 2 SMAX slots on each side
+    for (int q = threadIdx.x; q < 4 * SMAX; q += WGS) {
+      const int s = q < 2 * SMAX ? q : off + nd + (q - 2 * SMAX);
+      if ((q < 2 * SMAX && s < off) || (q >= 2 * SMAX && s < ndw))
+        *(l_u32 *)(V + mf_vaddr(4 * s)) = 0u;
     }
 #pragma unroll
     for (int j = 0; j < MF_PF; ++j) {
