@@ -32,10 +32,11 @@ enum { C_SIGMA = 0, C_NSIGMA, C_R, C_NB, C_TAU, C_ONE, NCONST };
 // coefficient-row flag (six 64-bit words: generation and one header word of
 // each new row), workgroup r using copy r mod NSPLIT so that no single line
 // takes every workgroup's atomics or polls; the error word and the Horner
-// completion counter
+// completion counter, and the generation of group frames the leader has
+// cleared
 constexpr int NSPLIT = 8;
 enum { SY_ARRIVE = 0, SY_FLAG = 32 * NSPLIT, SY_HFLAG = 64 * NSPLIT, SY_ERROR = 96 * NSPLIT,
-       SY_HDONE = 96 * NSPLIT + 32, SY_WORDS = 96 * NSPLIT + 64 };
+       SY_HDONE = 96 * NSPLIT + 32, SY_CLEAR = 96 * NSPLIT + 64, SY_WORDS = 96 * NSPLIT + 96 };
 
 enum { MODE_INTEGRATE = 0, MODE_COEFFS = 1, MODE_ADJOINT = 2 };
 

@@ -1231,12 +1231,19 @@ __device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, G
     const long long *pend = nullptr;  // the previous index's group frames
     for (int i = 0; i < I.N; ++i) {
       if (tid < NFR) lds_put(cv.fd + tid, late_desc(I, cv, tid, i, err));
-      if (pend && wave > 0) {
+      if (pend && wave == 1) {
+        // the previous index's group frames, next used by index i+1 (frame
+        // generation gs.nbulk + 2), whose early products the followers add
+        // in as soon as this clear is published
         for (int f = 0; f < NFR; ++f) {
           long long *fr = const_cast<long long *>(pend) + (size_t)f * WB;
           const int nc = ccols[f];
-          for (int c = tid - 64; c < nc; c += WGS - 64) st_relaxed(fr + c, 0LL);
+          for (int c = tid - 64; c < nc; c += 64) st_relaxed(fr + c, 0LL);
         }
+        wait_vmem();
+        if (tid == 64)
+          __hip_atomic_store(I.sync + SY_CLEAR, (uint32_t)(gs.nbulk + 2), __ATOMIC_RELEASE,
+                             __HIP_MEMORY_SCOPE_AGENT);
       }
       prof_mark(I, cv, PH_SETUP);
       ++gs.nbulk;
@@ -1339,6 +1346,31 @@ __device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, G
       if (tp && tid == 0) {
         atomicAdd(tp + 2, *tmx);  // slowest thread's products
         *tmx = 0;
+      }
+      // the early columns go into the group frames of index j now (frame
+      // generation gs.nbulk + 1, cleared by the leader once index j-2 was
+      // finalised), so that only the late ones wait for rows j
+      {
+        const unsigned long long B = gs.nbulk + 1;
+        if (tid == 0) spin_until(I.sync + SY_CLEAR, (uint32_t)B, err);
+        __syncthreads();
+        long long *gf = I.gframes + (size_t)(B & 1) * NFR * I.WB;
+        l_i32 *es = (l_i32 *)cv.span + 2 * NFR;
+        for (int f = 0; f < 2; ++f) {
+          const int c0 = es[2 * f], c1 = es[2 * f + 1];
+          for (int c = c0 + tid; c < c1; c += WGS) {
+            l_i64 *lc = (l_i64 *)cv.lf + (size_t)f * I.WB + c;
+            const long long v = *lc;
+            if (v != 0) {
+              __hip_atomic_fetch_add((unsigned long long *)(gf + (size_t)f * I.WB + c),
+                                     (unsigned long long)v, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+              *lc = 0;
+            }
+          }
+        }
+        __syncthreads();
+        if (tid < 4) es[tid] = 0;
       }
       prof_mark(I, cv, PH_FINAL);
     }
