@@ -1046,7 +1046,8 @@ __device__ __forceinline__ void late_step(const Inst &I, const Carve &cv, int ra
 // is multiplied) and its wavefronts split the U blocks.  Terms k0..k1-1.
 template <int NQA, int JQA, int NQB, int JQB>
 __device__ void mfma_terms(const Inst &I, const Carve &cv, int rank, int j, int k0, int k1,
-                           const MfGeo &g, const MfPrefetch *first) {
+                           const MfGeo &g, const MfPrefetch *first, long long *gf, uint32_t gen,
+                           uint32_t *err) {
   const int tid = threadIdx.x, nd = I.nd;
   const l_i32 *ha = (const l_i32 *)hc_row(I, cv, 0), *hb = (const l_i32 *)hc_row(I, cv, 1),
               *hg = (const l_i32 *)hc_row(I, cv, 2);
@@ -1074,6 +1075,10 @@ __device__ void mfma_terms(const Inst &I, const Carve &cv, int rank, int j, int 
     }
   };
   int32_t *P = (int32_t *)(cv.stage + 2 * (size_t)g.BUF);
+  // the piece sums go straight into the group frames of index j (frame
+  // generation gen), once the leader has published their clear; the first
+  // barrier below orders this wait before every add
+  if (tid == 0) spin_until(I.sync + SY_CLEAR, gen, err);
   MfPrefetch pf;
   if (first) pf = *first;
   else mf_load(pf, row_ptr(I, 0, j - k0), row_ptr(I, 2, k0), row_ptr(I, 1, k0), nd);
@@ -1091,7 +1096,7 @@ __device__ void mfma_terms(const Inst &I, const Carve &cv, int rank, int j, int 
     if (++cnt == g.FT) {
       mf_flush<2>(acc, P, g);
       __syncthreads();
-      mf_columns(P, cv.lf, I.WB, g);
+      mf_columns_global(P, gf, I.WB, g);
       cnt = 0;
       mark(12);
     }
@@ -1099,7 +1104,7 @@ __device__ void mfma_terms(const Inst &I, const Carve &cv, int rank, int j, int 
   if (cnt > 0) {
     mf_flush<2>(acc, P, g);
     __syncthreads();
-    mf_columns(P, cv.lf, I.WB, g);
+    mf_columns_global(P, gf, I.WB, g);
   }
   mark(12);
 }
@@ -1108,24 +1113,25 @@ __device__ void mfma_terms(const Inst &I, const Carve &cv, int rank, int j, int 
 // the operand counts of this row size (every size mf_fits admits is one of
 // the cases below).
 __device__ __forceinline__ void mfma_early(const Inst &I, const Carve &cv, int rank, int j, uint32_t *err,
-                                           const MfPrefetch *first) {
+                                           const MfPrefetch *first, long long *gf, uint32_t gen) {
   const int tid = threadIdx.x;
   const MfGeo g = mf_geo(I.nd);
   const int n = j - 1;
   const unsigned W = (unsigned)(I.G - 1), r = (unsigned)(rank - 1);
   const int k0 = 1 + (int)(((unsigned long long)n * r) / W);
   const int k1 = 1 + (int)(((unsigned long long)n * (r + 1)) / W);
+  // the products go straight to the group frames: no early columns in LDS
   if (tid < 2) {
     l_i32 *es = (l_i32 *)cv.span + 2 * NFR + 2 * tid;
     es[0] = 0;
-    es[1] = k1 > k0 ? min(I.WB, 256 * g.NT + 1) : 0;
+    es[1] = 0;
   }
   if (k1 <= k0) return;
   const int key = ((g.NQA * 8 + g.JQA) * 8 + g.NQB) * 8 + g.JQB;
   switch (key) {
 #define MF_CASE(a, b, c, d)                                        \
   case ((a * 8 + b) * 8 + c) * 8 + d:                              \
-    mfma_terms<a, b, c, d>(I, cv, rank, j, k0, k1, g, first);      \
+    mfma_terms<a, b, c, d>(I, cv, rank, j, k0, k1, g, first, gf, gen, err); \
     break;
     MF_CASE(1, 0, 1, 0)
     MF_CASE(1, 0, 2, 0)
@@ -1338,7 +1344,8 @@ __device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, G
       unsigned long long *tp = I.prof && rank == 1 ? I.prof + PH_NPHASE + 9 : nullptr;
       unsigned long long *tmx = (unsigned long long *)(cv.red + 32);
       if (I.mfma & 1)
-        mfma_early(I, cv, rank, j, err, have_pre ? &pre : nullptr);
+        mfma_early(I, cv, rank, j, err, have_pre ? &pre : nullptr,
+                   I.gframes + (size_t)((gs.nbulk + 1) & 1) * NFR * I.WB, (uint32_t)(gs.nbulk + 1));
       else
         frames_accumulate(cv.fs + NFR, cv.fd + NFR, 2, nd, RS, I.WB, cv.lf, rank, I.G,
                           cv.span + 2 * NFR, true, tp, tmx);

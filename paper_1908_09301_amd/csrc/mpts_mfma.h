@@ -336,6 +336,27 @@ __device__ __forceinline__ void mf_flush(mf_v16i (&acc)[NF][MF_NTMAX], int32_t *
     }
 }
 
+// Add the piece sums into the frames' 64-bit columns of the group's frames
+// in global memory, gf[f * WB + c] (column c = pi / 4 with weight
+// 2^(7 (pi % 4)); device-scope atomic adds), and clear them; every thread
+// of the workgroup, after every wavefront's mf_flush.
+__device__ __forceinline__ void mf_columns_global(int32_t *P, long long *gf, int WB, const MfGeo &g) {
+  const int ncol = g.NT * 256;
+  for (int w = threadIdx.x; w < 2 * ncol; w += WGS) {
+    const int f = w >= ncol ? 1 : 0, c = w - f * ncol;
+    l_v4i16 *pp = (l_v4i16 *)((l_i32 *)P + f * g.NT * 1024 + 4 * c);
+    const mf_v4i v = *pp;
+    if ((v.x | v.y | v.z | v.w) != 0) {
+      const long long s = (long long)v.x + (long long)v.y * 128LL + (long long)v.z * 16384LL +
+                          (long long)v.w * 2097152LL;
+      if (c < WB && s != 0)
+        __hip_atomic_fetch_add((unsigned long long *)(gf + (size_t)f * WB + c), (unsigned long long)s,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      *pp = mf_v4i{0, 0, 0, 0};
+    }
+  }
+}
+
 // Move the piece sums into the frames' 64-bit LDS columns lf[f * WB + c]
 // (column c = pi / 4 with weight 2^(7 (pi % 4))) and clear them; every
 // thread of the workgroup, after every wavefront's mf_flush.
