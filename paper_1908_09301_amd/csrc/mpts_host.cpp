@@ -376,7 +376,7 @@ size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 constexpr int kMaxWG = 4096;
 constexpr size_t kLdsPerCU = 160 * 1024;  // LDS one gfx950 workgroup can hold
-constexpr int kMfmaMinDigits = 320;       // rows from which the matrix cores take the early products
+constexpr int kMfmaMinDigits = 140;       // rows from which the matrix cores take the early products
 
 // Workspace of one trajectory.  The parts every call uses come first (the
 // batch takes a region up to `inst` per trajectory); the coefficient output

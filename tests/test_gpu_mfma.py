@@ -3,7 +3,7 @@ blocks, i32 accumulators flushed into 64-bit columns) against the oracle and
 against the VALU tile path, bit for bit (GPU).
 
 MPTS_EARLY=valu or =mfma, read when a context is created, selects the
-path; by default a context whose rows have at least 300 digits and fit the
+path; by default a context whose rows have at least 140 digits and fit the
 matrix-core accumulators (at most 487 digits, L <= 425 limbs) uses the
 matrix cores whenever its trajectory runs on two or more workgroups."""
 import os
