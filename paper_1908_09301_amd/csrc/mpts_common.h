@@ -69,6 +69,9 @@ struct Inst {
   int loss;           // adjoint seed: 0 = 2 x(T) (squared norm), 1..3 = unit vector e_x, e_y, e_z
   int mfma;           // bit 0: early Cauchy products on the int8 matrix cores (else VALU tiles)
   int next;           // batch: 1 + index of the instance the same workgroups run next (0: none)
+  // rational step size (tau_d > 0): d tau = n + (m1 2^28 + m0) 2^(28 e)
+  // exactly, so tau h = (n h + (m1 2^28 + m0) 2^(28 e) h) / d
+  int tau_n, tau_d, tau_m0, tau_m1, tau_e;
   long long nsteps;
   int32_t *rows;      // [3][N+1][RS]
   int32_t *consts;    // [NCONST][RS]

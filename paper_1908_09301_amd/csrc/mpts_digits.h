@@ -270,29 +270,24 @@ __device__ __forceinline__ int mulmod(int a, int b, double dd, double inv) {
   return (int)m;
 }
 
-// The quotient part of div_to_row: the dividend is D[lowcut..t] (in LDS
-// scratch sc) shifted up by m zero digits, C2 digits per lane.
-template <int C2>
-__device__ __forceinline__ bool div_window(const l_i32 *sc, int t, int lowcut, int m, bool low_nz,
-                                           int sign, long long base, int dv, int L, int nd, int RS,
-                                           int32_t *row) {
+// Divide the magnitude D (lane l: digits [l C, l C + C)) by dv in place,
+// 1 <= dv < 2^13; returns whether the remainder is nonzero (uniform).  The
+// division runs in parallel: each lane's chunk remainder, a scan of the
+// chunk maps x -> (x 2^(28 C) + r_l) mod dv from the top lane down, then
+// each lane's quotient digits.
+template <int C>
+__device__ __forceinline__ bool div_small_c(int (&x)[C], int dv) {
   const int lane = lane_id();
   const double dd = (double)dv, inv = 1.0 / dd;
-  int x[C2];
-#pragma unroll
-  for (int j = 0; j < C2; ++j) {
-    const int k = lane * C2 + j - m + lowcut;
-    x[j] = (k >= lowcut && k <= t) ? sc[k] : 0;
-  }
   // chunk remainder, from the top digit down
   int r = 0;
 #pragma unroll
-  for (int j = C2 - 1; j >= 0; --j) (void)divmod_f64(r, x[j], dd, inv, &r);
-  // P = 2^(28 C2) mod d
+  for (int j = C - 1; j >= 0; --j) (void)divmod_f64(r, x[j], dd, inv, &r);
+  // P = 2^(28 C) mod d
   const int b28 = (int)((1LL << DBITS) % dv);
   int P = 1 % dv;
 #pragma unroll
-  for (int j = 0; j < C2; ++j) P = mulmod(P, b28, dd, inv);
+  for (int j = 0; j < C; ++j) P = mulmod(P, b28, dd, inv);
   // suffix scan: (A, Bv) maps x -> (A x + Bv) mod d over lanes [lane, 63]
   int A = P, Bv = r;
 #pragma unroll
@@ -310,8 +305,24 @@ __device__ __forceinline__ bool div_window(const l_i32 *sc, int t, int lowcut, i
   // quotient digits
   r = rin;
 #pragma unroll
-  for (int j = C2 - 1; j >= 0; --j) x[j] = divmod_f64(r, x[j], dd, inv, &r);
-  const bool sticky = (__shfl(r, 0, 64) != 0) || low_nz;
+  for (int j = C - 1; j >= 0; --j) x[j] = divmod_f64(r, x[j], dd, inv, &r);
+  return __shfl(r, 0, 64) != 0;
+}
+
+// The quotient part of div_to_row: the dividend is D[lowcut..t] (in LDS
+// scratch sc) shifted up by m zero digits, C2 digits per lane.
+template <int C2>
+__device__ __forceinline__ bool div_window(const l_i32 *sc, int t, int lowcut, int m, bool low_nz,
+                                           int sign, long long base, int dv, int L, int nd, int RS,
+                                           int32_t *row) {
+  const int lane = lane_id();
+  int x[C2];
+#pragma unroll
+  for (int j = 0; j < C2; ++j) {
+    const int k = lane * C2 + j - m + lowcut;
+    x[j] = (k >= lowcut && k <= t) ? sc[k] : 0;
+  }
+  const bool sticky = div_small_c<C2>(x, dv) || low_nz;
   return round_to_row<C2>(x, sign, base + lowcut - m, sticky, L, nd, RS, row);
 }
 

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <atomic>
 #include <map>
+#include <numeric>
 #include <tuple>
 #include <mutex>
 #include <cmath>
@@ -339,6 +340,9 @@ struct mpts_ctx {
   int L, N, nd, RS, WB, CM;
   uint64_t gen = 0;          // creation number, never reused (keys the graph cache)
   int mfma = 0;              // 1: early Cauchy products on the int8 matrix cores
+  // step size n/d with small n, d (tau_d > 0; else 0): d tau_p = n + r 2^E
+  // exactly, tau_m1 2^28 + tau_m0 = r 2^(E - 28 tau_e), tau_e = floor(E / 28)
+  int tau_n = 0, tau_d = 0, tau_m0 = 0, tau_m1 = 0, tau_e = 0;
   std::vector<int32_t> cn;  // NCONST x (L+2) normalised constants
   int wgs = 0;
   int cus = 0;
@@ -458,6 +462,56 @@ int nv_to_bf(const mpts_ctx *c, const int32_t *nv, mpts_bf *b) {
   return MPTS_OK;
 }
 
+// The rounded step size tau_p = M 2^E (nv: sign, E, M of L limbs) of a
+// step size n/d with n < 2^27, d < 2^13 satisfies d tau_p = n + r 2^E with
+// r = d M - n 2^-E, |r| <= d / 2 (M is n 2^-E / d rounded to an integer).
+// Each Horner step round(tau_p h + c) of equation (2) is then
+// round((n h + r 2^E h + d c) / d): three multiples of rows by small
+// integers and one short division instead of a p x p-bit product.  Leaves
+// tau_d = 0 (the full product) for other step sizes and under
+// MPTS_TAU=product.
+void tau_rational(const Rational &q, const std::vector<int32_t> &nv, int L, mpts_ctx *c) {
+  c->tau_d = 0;
+  const char *env = getenv("MPTS_TAU");
+  if (env && strcmp(env, "product") == 0) return;
+  if (nv[0] == 0 || q.num.size() > 2 || q.den.size() > 2) return;
+  auto u64 = [](const Big &a) {
+    uint64_t v = 0;
+    for (size_t i = a.size(); i-- > 0;) v = (v << 32) | a[i];
+    return v;
+  };
+  uint64_t n = u64(q.num), d = u64(q.den);
+  const uint64_t g = std::gcd(n, d);
+  n /= g;
+  d /= g;
+  const long long E = nv[1];
+  if (n == 0 || n >= (1u << 27) || d == 0 || d >= (1u << 13) || E > 0) return;
+  Big M(nv.begin() + 2, nv.begin() + 2 + L);
+  trim(M);
+  Big dM = M;
+  mul_small_add(dM, (uint32_t)d, 0u);
+  const Big nk = shl(Big{(uint32_t)n}, -E);
+  Big r;
+  int rs = 1;
+  if (cmp(dM, nk) >= 0) {
+    r = dM;
+    sub_in(r, nk);
+  } else {
+    r = nk;
+    sub_in(r, dM);
+    rs = -1;
+  }
+  if (bitlen(r) > 31) return;
+  const long long eE = E >= 0 ? E / DBITS : -((-E + DBITS - 1) / DBITS);
+  const int tE = (int)(E - eE * DBITS);
+  const long long m = (long long)nv[0] * rs * (long long)(r.empty() ? 0u : r[0]) * (1LL << tE);
+  c->tau_n = nv[0] * (int)n;
+  c->tau_d = (int)d;
+  c->tau_m0 = (int)(m & (long long)DMASK);
+  c->tau_m1 = (int)(m >> DBITS);
+  c->tau_e = (int)eE;
+}
+
 int make_ctx(const char *sigma, const char *R, const char *b, int L, int N, const char *tau,
              mpts_ctx **out) {
   if (!out) return MPTS_EINVAL;
@@ -510,6 +564,7 @@ int make_ctx(const char *sigma, const char *R, const char *b, int L, int N, cons
   put(C_NB, nv);
   round_rational(qt, 0, L, nv);
   put(C_TAU, nv);
+  tau_rational(qt, nv, L, c);
   Rational one;
   one.num = Big{1u};
   one.den = Big{1u};
@@ -596,6 +651,11 @@ int run_single(mpts_ctx *c, int mode, long long nsteps, const void *x0_dev, void
   I.loss = loss;
   I.mfma = c->mfma;
   I.nsteps = nsteps;
+  I.tau_n = c->tau_n;
+  I.tau_d = c->tau_d;
+  I.tau_m0 = c->tau_m0;
+  I.tau_m1 = c->tau_m1;
+  I.tau_e = c->tau_e;
   I.rows = (int32_t *)(base + l.rows);
   I.consts = (int32_t *)(base + l.consts);
   I.cnorm = (int32_t *)(base + l.cnorm);
@@ -641,7 +701,7 @@ int read_status(mpts_ctx *c, void *ws, hipStream_t s) {
       (void)hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev);
       double us = rate > 0 ? 1e3 / rate : 0.0;  // rate in kHz
       static const char *nm[16] = {"setup", "accum", "flush", "wait", "final", "release", "horner",
-                                   "step0", "spare", "f.round1", "f.res2", "f.div", "f.row", "h.prod", "h.setup", "h.round"};
+                                   "step0", "spare", "f.round1", "f.res2", "f.div", "f.row", "h.prod", "h.div", "h.round"};
       fprintf(stderr, "mpts phases (us):");
       for (int w2 = 0; w2 < 2; ++w2) {
         fprintf(stderr, w2 ? "\n  wg1:" : "\n  leader:");
@@ -1396,6 +1456,11 @@ int mpts_integrate_batch(mpts_ctx *const *ctxs, int32_t count, const mpts_bf *x0
     I.mode = MODE_INTEGRATE;
     I.mfma = c->mfma;
     I.nsteps = nsteps[t];
+    I.tau_n = c->tau_n;
+    I.tau_d = c->tau_d;
+    I.tau_m0 = c->tau_m0;
+    I.tau_m1 = c->tau_m1;
+    I.tau_e = c->tau_e;
     I.rows = (int32_t *)(rb + l.rows);
     I.consts = (int32_t *)(rb + l.consts);
     I.cnorm = (int32_t *)(rb + l.cnorm);
@@ -1623,6 +1688,11 @@ int mpts_grad_batch(mpts_ctx *const *ctxs, int32_t count, const mpts_bf *x0, con
     I.loss = loss;
     I.mfma = c->mfma;
     I.nsteps = nsteps[t];
+    I.tau_n = c->tau_n;
+    I.tau_d = c->tau_d;
+    I.tau_m0 = c->tau_m0;
+    I.tau_m1 = c->tau_m1;
+    I.tau_e = c->tau_e;
     I.rows = (int32_t *)(rb + l.rows);
     I.consts = (int32_t *)(rb + l.consts);
     I.cnorm = (int32_t *)(rb + l.cnorm);

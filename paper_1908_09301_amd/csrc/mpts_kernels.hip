@@ -299,6 +299,97 @@ __device__ __forceinline__ bool sum_to_row(const long long *frame, bool frame_gl
   return ok;
 }
 
+// A rational step size: d tau = n + m 2^(28 e) exactly, m = m1 2^28 + m0
+// (0 <= m0 < 2^28, |n| < 2^27, 1 <= d < 2^13).
+struct TauQ {
+  int n, m0, m1, e, dv;
+};
+
+// One step h <- round(tau h + c) of equation (2) for a rational step size
+// (c: an LDS row, or null for h <- round(tau h)), in place on the LDS row
+// h.  The exact value tau h + c is (n h + m 2^(28 e) h + d c) / d: the
+// numerator's columns are gathered straight into registers (each a sum of
+// four digit multiples, |v| < 2^57), resolved, divided by d in registers and
+// rounded once.  A numerator with fewer than p + 15 bits above its lowest
+// column (cancellation) goes through div_to_row, which extends it with zero
+// digits.  Single wavefront; scratch: 64 CM LDS digits.
+template <int CM, typename Mark>
+__device__ __forceinline__ bool tau_step_rational(const TauQ &q, int L, int nd, int RS, int32_t *h_,
+                                                  const int32_t *c_, int32_t *scratch,
+                                                  uint32_t *err, Mark &&mark) {
+  const int lane = lane_id();
+  const l_i32 *h = (const l_i32 *)h_;
+  const int eh = h[0], sh = h[1];
+  const int ec = c_ ? ((const l_i32 *)c_)[0] : 0, sc = c_ ? ((const l_i32 *)c_)[1] : 0;
+  const bool mterm = q.m0 != 0 || q.m1 != 0;
+  // window: the m term lies about p bits below n h; without it, one zero
+  // digit below the lowest operand keeps p + 2 quotient bits
+  long long lo = 1LL << 40, hi = -(1LL << 40);
+  if (sh != 0) {
+    lo = mterm ? (long long)eh + q.e : (long long)eh - 1;
+    hi = (long long)eh + nd + 1;  // n h: |n| < 2^27 adds one digit
+    if (mterm) hi = max(hi, (long long)eh + q.e + nd + 1);
+  }
+  if (sc != 0) {
+    lo = min(lo, (long long)ec - 1);
+    hi = max(hi, (long long)ec + nd + 1);
+  }
+  int C = 2;
+  bool ok = true;
+  if (lo > hi) {
+    lo = 0;
+  } else if (hi - lo + 2 > 64LL * CM) {
+    if (lane == 0) atomicOr(err, 1u | 32u);
+    ok = false;
+    lo = 0;
+  } else {
+    const int W = (int)(hi - lo + 2);
+    C = W > 128 ? (W + 63) >> 6 : 2;
+  }
+  const bool any = ok && (sh != 0 || sc != 0);
+  with_chunks<CM>(C, [&](auto ct) {
+    constexpr int Ct = decltype(ct)::value;
+    long long v[Ct];
+#pragma unroll
+    for (int j = 0; j < Ct; ++j) v[j] = 0;
+    if (any) {
+      // rows carry RPAD >= Ct + 1 zero digits on each side (and a zero row
+      // has zero digits): a chunk that overlaps the digits is read whole,
+      // one that does not is pointed at the zeros, so no read is predicated
+      const l_i32 *hd = h + HDR + RPAD;
+      int kh = (int)(lo - eh) + lane * Ct;
+      int km = kh - q.e;
+      kh = min(max(kh, -Ct), nd);
+      km = min(max(km, -Ct), nd + 1);
+#pragma unroll
+      for (int j = 0; j < Ct; ++j)
+        v[j] = (long long)q.n * hd[kh + j] + (long long)q.m0 * hd[km + j] +
+               (long long)q.m1 * hd[km + j - 1];
+      if (c_) {
+        const l_i32 *cd = (const l_i32 *)c_ + HDR + RPAD;
+        int kc = (int)(lo - ec) + lane * Ct;
+        kc = min(max(kc, -Ct), nd);
+#pragma unroll
+        for (int j = 0; j < Ct; ++j) v[j] += (long long)q.dv * cd[kc + j];
+      }
+    }
+    int d[Ct];
+    bool ovf = false;
+    const int sgn = resolve_c<Ct>(v, d, &ovf);
+    if (ovf && lane == 0) atomicOr(err, 1u | 64u);
+    mark(13);
+    const int B = sgn != 0 ? top_bit_c<Ct>(d) : -1;
+    if (B >= 32 * L + 15) {
+      const bool sticky = div_small_c<Ct>(d, q.dv);
+      ok &= round_to_row<Ct>(d, sgn, lo, sticky, L, nd, RS, h_);
+    } else {
+      ok &= div_to_row<Ct, CM>(d, sgn, lo, q.dv, L, nd, RS, scratch, h_);
+    }
+    mark(14);
+  });
+  return ok;
+}
+
 // Normalised value [sign, E, M] of an LDS row (exact: a row holds p bits).
 // scratch: 64 CM digits of LDS; out: L + 2 words of LDS.  Single wavefront.
 template <int CM>
@@ -1386,6 +1477,57 @@ __device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, G
   }
 }
 
+// The Horner chains (mode 0) or the adjoint's powers of tau (mode 1) for a
+// rational step size: chain c0 + w on wavefront w < nc, the coefficient
+// rows c_i staged into LDS by wavefront 3, every operand read once into
+// registers.
+template <int CM>
+__device__ __noinline__ void tau_chains_rational(const Inst &I, const Carve &cv, int count,
+                                                 int mode, uint32_t *err, int c0, int nc) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int L = I.L, nd = I.nd, RS = I.RS, N = I.N;
+  const TauQ q{I.tau_n, I.tau_m0, I.tau_m1, I.tau_e, I.tau_d};
+  const bool rel = I.G > 1;
+  const int32_t *rows = I.rows;
+  int32_t *qrows = mode == 1 ? q_row(I, 0, 0) : nullptr;
+  unsigned long long *prof = (I.prof != nullptr && tid == 0 && blockIdx.x == I.wg0) ? I.prof : nullptr;
+  int32_t *const abuf = cv.trow;
+  int32_t *const h = cv.hrow + (size_t)(c0 + (wave < nc ? wave : 0)) * RS;
+  int32_t *const scratch = (int32_t *)(cv.tcols + (size_t)wave * 64 * I.CM);
+  unsigned long long tq = prof ? wall_clock64() : 0;
+  auto sub = [&](int slot) {
+    if (prof) {
+      const unsigned long long t = wall_clock64();
+      atomicAdd(prof + slot, t - tq);
+      tq = t;
+    }
+  };
+  // coefficient rows c_i (i = N-1-it) into LDS buffer it & 1
+  auto stage = [&](int it_, int t0, int tstep) {
+    int32_t *dst = abuf + (size_t)(it_ & 1) * nc * RS;
+    for (int f = 0; f < nc; ++f) {
+      const g_i32 *src = (const g_i32 *)(rows + ((long long)(c0 + f) * (N + 1) + (N - 1 - it_)) * RS);
+      for (int w = t0; w < RS; w += tstep) ((l_i32 *)dst)[(size_t)f * RS + w] = src[w];
+    }
+  };
+  if (mode == 0 && count > 0) {
+    stage(0, tid, WGS);
+    __syncthreads();
+  }
+  for (int it = 0; it < count; ++it) {
+    if (mode == 0 && wave == 3 && it + 1 < count) stage(it + 1, lane, 64);
+    if (wave < nc) {
+      const int32_t *ad = mode == 0 ? abuf + (size_t)((it & 1) * nc + wave) * RS : nullptr;
+      if (!tau_step_rational<CM>(q, L, nd, RS, h, ad, scratch, err, sub) && lane == 0)
+        atomicOr(err, 2u);
+      if (mode == 1)
+        publish_row(h, qrows + ((long long)(c0 + wave) * (N + 1) + it + 1) * RS, RS, rel);
+    }
+    __syncthreads();
+    sub(15);
+  }
+}
+
 // Three single-workgroup chains at once on the leader: h_c <- round(tau h_c
 // + addend_c(i)) for `count` iterations.  h_c starts as the row start_c (an
 // LDS row in cv.hrow[c] must already hold it).  Used for the Horner sums of
@@ -1395,6 +1537,10 @@ template <int CM>
 __device__ __noinline__ void tau_chains(const Inst &I, const Carve &cv, int count, int mode,
                                         uint32_t *err,
                            int c0 = 0, int nc = 3) {
+  if (I.tau_d > 0) {
+    tau_chains_rational<CM>(I, cv, count, mode, err, c0, nc);
+    return;
+  }
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int L = I.L, nd = I.nd, RS = I.RS, WB = I.WB, N = I.N;
   const int32_t *tau_lds = cv.hrow + (size_t)3 * RS;
