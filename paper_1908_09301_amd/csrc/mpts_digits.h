@@ -179,10 +179,25 @@ __device__ __forceinline__ int top_bit_c(const int (&d)[C]) {
   return (tl * C + hj) * DBITS + (31 - __clz(dt));
 }
 
+// Digit k of D (uniform k, 0 <= k < 64 C), read on every lane.
+template <int C>
+__device__ __forceinline__ int digit_at(const int (&d)[C], int k) {
+  const int kl = k / C, kj = k - kl * C;
+  int v = 0;
+#pragma unroll
+  for (int j = 0; j < C; ++j) v = j == kj ? d[j] : v;
+  return __builtin_amdgcn_readlane(v, kl);
+}
+
 // Round sign * D * 2^(28 base) to p = 32 L bits (nearest, ties to even;
 // sticky_in: a nonzero value below D) and write it as a row into the LDS
 // row `row` (RS words).  D must have a zero top digit (room for the carry of
 // rounding up).  Returns false on exponent overflow.
+//
+// The round bit and the last kept bit sit in two digits whose indices are
+// uniform, so they are read once (readlane) instead of tested in every
+// digit; the kept part is at least 32 bits long, so rounding up changes the
+// top bit only through a carry out of the cut digit (rare, general path).
 template <int C>
 __device__ __forceinline__ bool round_to_row(int (&d)[C], int sign, long long base, bool sticky_in,
                                              int L, int nd, int RS, int32_t *row_) {
@@ -201,25 +216,28 @@ __device__ __forceinline__ bool round_to_row(int (&d)[C], int sign, long long ba
     const int rb = shc - 1;
     const int kr = rb / DBITS, rr = rb - kr * DBITS;
     const int kc = shc / DBITS, rc = shc - kc * DBITS;
-    const uint32_t rmask = (1u << rr) - 1u, cmask = ~((1u << rc) - 1u);
-    bool s = false, rbit = false, lsb = false;
+    const int xr = digit_at<C>(d, kr), xc = digit_at<C>(d, kc);
+    // sticky: the bits of digit kr below the round bit and every digit below kr
+    int below = 0;
+#pragma unroll
+    for (int j = 0; j < C; ++j) below |= k0 + j < kr ? d[j] : 0;
+    const bool sticky = sticky_in || (xr & ((1 << rr) - 1)) != 0 || __ballot(below != 0) != 0ull;
+    const bool up = ((xr >> rr) & 1) && (sticky || ((xc >> rc) & 1));
+    int xcut = xc & ~((1 << rc) - 1);
+    if (up) xcut += 1 << rc;
+    const bool carry = (xcut >> DBITS) != 0;  // uniform
+    // digits below kc cleared, digit kc replaced
 #pragma unroll
     for (int j = 0; j < C; ++j) {
       const int k = k0 + j;
-      const uint32_t x = (uint32_t)d[j];
-      s |= (k < kr && x != 0u) || (k == kr && (x & rmask) != 0u);
-      rbit |= k == kr && ((x >> rr) & 1u);
-      lsb |= k == kc && ((x >> rc) & 1u);
-      d[j] = k < kc ? 0 : (k == kc ? (int)(x & cmask) : (int)x);
+      d[j] = k < kc ? 0 : (k == kc ? (xcut & (int)DMASK) : d[j]);
     }
-    const bool sticky = sticky_in || __ballot(s) != 0ull;
-    const bool up = __ballot(rbit) != 0ull && (sticky || __ballot(lsb) != 0ull);
-    if (up) {
-      // + 2^rc at digit kc, carried through the digits and across lanes
+    if (carry) {
+      // + 1 at digit kc + 1, carried through the digits and across lanes
       int x = 0;
 #pragma unroll
       for (int j = 0; j < C; ++j) {
-        const int t = d[j] + x + (k0 + j == kc ? (1 << rc) : 0);
+        const int t = d[j] + x + (k0 + j == kc + 1 ? 1 : 0);
         d[j] = t & (int)DMASK;
         x = t >> DBITS;
       }
@@ -229,11 +247,15 @@ __device__ __forceinline__ bool round_to_row(int (&d)[C], int sign, long long ba
   }
   const int Erel = B + 1 - p;  // exponent of the mantissa's last bit, relative to D
   const int erel = Erel >= 0 ? Erel / DBITS : -((-Erel + DBITS - 1) / DBITS);
-  // row digit (k - erel) = sign * D[k]; every nonzero digit of D lies in the row
+  // row digit (k - erel) = sign * D[k]; every nonzero digit of D lies in the
+  // row, so positions outside it (clamped into the zero padding) get zeros
+  l_i32 *rd = row + HDR + RPAD;
 #pragma unroll
   for (int j = 0; j < C; ++j) {
     const int r = k0 + j - erel;
-    if (d[j] != 0 && r >= 0 && r < nd) row[HDR + RPAD + r] = sign < 0 ? -d[j] : d[j];
+    const int rcl = min(max(r, -1), nd);
+    const int val = sign < 0 ? -d[j] : d[j];
+    rd[rcl] = r == rcl ? val : 0;
   }
   if (lane == 0) {
     row[0] = (int32_t)(base + erel);
@@ -244,69 +266,96 @@ __device__ __forceinline__ bool round_to_row(int (&d)[C], int sign, long long ba
   return E > -(1LL << 30) && E < (1LL << 30);
 }
 
-__device__ __forceinline__ int divmod_f64(int r, int x, double dd, double inv, int *rem) {
-  // floor((r 2^28 + x) / d) and the remainder, 0 <= r < d < 2^13, 0 <= x < 2^28
-  const double n = fma((double)r, 268435456.0, (double)x);  // exact (< 2^41)
-  double q = floor(n * inv);
-  double m = fma(-q, dd, n);  // exact
-  if (m < 0.0) {
-    q -= 1.0;
-    m += dd;
-  } else if (m >= dd) {
-    q += 1.0;
-    m -= dd;
-  }
-  *rem = (int)m;
-  return (int)q;
+// (r 2^28 + x) / d and its remainder for 0 <= r < d < 2^13, 0 <= x < 2^28,
+// in doubles (all exact).
+__device__ __forceinline__ double dstep(double r, double x, double dd, double inv, double *q) {
+  const double n = fma(r, 268435456.0, x);  // < 2^41
+  double qq = floor(n * inv);
+  double m = fma(-qq, dd, n);
+  const bool lo = m < 0.0, hi = m >= dd;
+  qq = lo ? qq - 1.0 : (hi ? qq + 1.0 : qq);
+  m = lo ? m + dd : (hi ? m - dd : m);
+  *q = qq;
+  return m;
 }
 
-__device__ __forceinline__ int mulmod(int a, int b, double dd, double inv) {
-  // (a b) mod d for 0 <= a, b < d < 2^13
-  const double n = (double)a * (double)b;
+// (a b + c) mod d for 0 <= a, b, c < d < 2^13, in doubles.  a b + c < 2^27,
+// so the quotient estimate is short by at most one.
+__device__ __forceinline__ double dmuladd(double a, double b, double c, double dd, double inv) {
+  const double n = fma(a, b, c);
   const double q = floor(n * inv);
-  double m = fma(-q, dd, n);
-  if (m < 0.0) m += dd;
-  else if (m >= dd) m -= dd;
-  return (int)m;
+  const double m = fma(-q, dd, n);
+  return m >= dd ? m - dd : m;
 }
 
 // Divide the magnitude D (lane l: digits [l C, l C + C)) by dv in place,
-// 1 <= dv < 2^13; returns whether the remainder is nonzero (uniform).  The
-// division runs in parallel: each lane's chunk remainder, a scan of the
-// chunk maps x -> (x 2^(28 C) + r_l) mod dv from the top lane down, then
-// each lane's quotient digits.
+// 1 <= dv < 2^13; returns whether the remainder is nonzero (uniform).  Each
+// lane's chunk is cut into blocks of S digits whose remainders are formed
+// side by side and folded; a scan over the lanes (from the top lane down,
+// x -> x 2^(28 C s) + r mod dv, with the uniform power 2^(28 C s) mod dv)
+// gives each lane its incoming remainder; each block's incoming remainder
+// then follows from it directly, and the blocks' quotient digits are again
+// formed side by side.
 template <int C>
 __device__ __forceinline__ bool div_small_c(int (&x)[C], int dv) {
+  constexpr int S = C >= 4 ? 4 : C;  // digits per block (C is 2, 4, 8, 12, 16, 24 or 32)
+  constexpr int NB = C / S;
   const int lane = lane_id();
   const double dd = (double)dv, inv = 1.0 / dd;
-  // chunk remainder, from the top digit down
-  int r = 0;
+  double xd[C];
 #pragma unroll
-  for (int j = C - 1; j >= 0; --j) (void)divmod_f64(r, x[j], dd, inv, &r);
-  // P = 2^(28 C) mod d
-  const int b28 = (int)((1LL << DBITS) % dv);
-  int P = 1 % dv;
+  for (int j = 0; j < C; ++j) xd[j] = (double)x[j];
+  // powers of 2^28 mod d: PS = 2^(28 S), PK[k] = PS^k, P = PS^NB
+  double qd;
+  const double b28 = dstep(dv > 1 ? 1.0 : 0.0, 0.0, dd, inv, &qd);
+  double PS = b28;
 #pragma unroll
-  for (int j = 0; j < C; ++j) P = mulmod(P, b28, dd, inv);
-  // suffix scan: (A, Bv) maps x -> (A x + Bv) mod d over lanes [lane, 63]
-  int A = P, Bv = r;
+  for (int t = 1; t < S; t <<= 1) PS = dmuladd(PS, PS, 0.0, dd, inv);
+  double PK[NB + 1];
+  PK[0] = dv > 1 ? 1.0 : 0.0;
+  PK[1] = PS;
+#pragma unroll
+  for (int k = 2; k <= NB; ++k) PK[k] = dmuladd(PK[k / 2], PK[k - k / 2], 0.0, dd, inv);
+  // block remainders, side by side
+  double rb[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    double r = 0.0;
+#pragma unroll
+    for (int j = S - 1; j >= 0; --j) r = dstep(r, xd[b * S + j], dd, inv, &qd);
+    rb[b] = r;
+  }
+  // fold from the top block: above[b] = the blocks above b, modulo d
+  double above[NB];
+  double r = 0.0;
+#pragma unroll
+  for (int b = NB - 1; b >= 0; --b) {
+    above[b] = r;
+    r = dmuladd(r, PS, rb[b], dd, inv);
+  }
+  // suffix scan over the lanes: lane l ends with lanes [l, 63], modulo d
+  double Ps = PK[NB];
 #pragma unroll
   for (int s = 1; s < 64; s <<= 1) {
-    const int A2 = __shfl_down(A, s, 64);
-    const int B2 = __shfl_down(Bv, s, 64);
-    if (lane + s < 64) {
-      const int sb = mulmod(A, B2, dd, inv) + Bv;
-      Bv = sb >= dv ? sb - dv : sb;
-      A = mulmod(A, A2, dd, inv);
-    }
+    const double r2 = (double)__shfl_down((int)r, s, 64);
+    if (lane + s < 64) r = dmuladd(Ps, r2, r, dd, inv);
+    Ps = dmuladd(Ps, Ps, 0.0, dd, inv);
   }
-  int rin = __shfl_down(Bv, 1, 64);
-  if (lane == 63) rin = 0;
-  // quotient digits
-  r = rin;
+  const int rup = __shfl_down((int)r, 1, 64);
+  const double rin = lane == 63 ? 0.0 : (double)rup;
+  // quotient digits, block by block side by side
+  double rlow = 0.0;
 #pragma unroll
-  for (int j = C - 1; j >= 0; --j) x[j] = divmod_f64(r, x[j], dd, inv, &r);
-  return __shfl(r, 0, 64) != 0;
+  for (int b = 0; b < NB; ++b) {
+    double rr = dmuladd(rin, PK[NB - 1 - b], above[b], dd, inv);
+#pragma unroll
+    for (int j = S - 1; j >= 0; --j) {
+      rr = dstep(rr, xd[b * S + j], dd, inv, &qd);
+      x[b * S + j] = (int)qd;
+    }
+    if (b == 0) rlow = rr;
+  }
+  return __builtin_amdgcn_readlane((int)rlow, 0) != 0;
 }
 
 // The quotient part of div_to_row: the dividend is D[lowcut..t] (in LDS
