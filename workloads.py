@@ -100,3 +100,62 @@ def random_limb_values(seed: int, count: int, L: int, spread_bits: int = 24):
         e = int(rng.integers(-spread_bits, spread_bits + 1)) - p
         out.append((s, m, e))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Polynomial vector fields of degree <= 2 (inputs only): each system is a
+# number of variables and a tuple of terms (equation, coefficient text,
+# u, w) meaning coef * x_u * x_w in dx_eq/dt (u, w = -1: absent).
+
+POLY_SYSTEMS = {
+    # the Lorenz system in this form (sigma (y - x), R x - y - x z, x y - b z)
+    "lorenz": (3, ((0, "-10", 0, -1), (0, "10", 1, -1), (1, "28", 0, -1), (1, "-1", 1, -1),
+                   (1, "-1", 0, 2), (2, "1", 0, 1), (2, "-8/3", 2, -1))),
+    # Roessler: x' = -y - z, y' = x + a y, z' = b + z x - c z (a = b = 0.2, c = 5.7)
+    "rossler": (3, ((0, "-1", 1, -1), (0, "-1", 2, -1), (1, "1", 0, -1), (1, "0.2", 1, -1),
+                    (2, "0.2", -1, -1), (2, "1", 2, 0), (2, "-5.7", 2, -1))),
+    # Chen: x' = a (y - x), y' = (c - a) x - x z + c y, z' = x y - b z (a = 35, b = 3, c = 28)
+    "chen": (3, ((0, "35", 1, -1), (0, "-35", 0, -1), (1, "-7", 0, -1), (1, "-1", 0, 2),
+                 (1, "28", 1, -1), (2, "1", 0, 1), (2, "-3", 2, -1))),
+    # a four-variable Roessler-type system: x' = -y - z, y' = x + 0.25 y + w,
+    # z' = 3 + x z, w' = -0.5 z + 0.05 w
+    "rossler4": (4, ((0, "-1", 1, -1), (0, "-1", 2, -1), (1, "1", 0, -1), (1, "0.25", 1, -1),
+                     (1, "1", 3, -1), (2, "3", -1, -1), (2, "1", 0, 2), (3, "-0.5", 2, -1),
+                     (3, "0.05", 3, -1))),
+    # closed forms: x' = x^2 (x(t) = x0 / (1 - x0 t)), x' = -x, and the
+    # harmonic oscillator x' = -y, y' = x
+    "square": (1, ((0, "1", 0, 0),)),
+    "decay": (1, ((0, "-1", 0, -1),)),
+    "oscillator": (2, ((0, "-1", 1, -1), (1, "1", 0, -1))),
+}
+
+POLY_X0 = {
+    "lorenz": BENCH_X0,
+    "rossler": ("1", "1", "1"),
+    "chen": ("-10", "0", "37"),
+    "rossler4": ("-10", "-6", "0", "10"),
+    "square": ("1/8",),
+    "decay": ("1",),
+    "oscillator": ("1", "0"),
+}
+
+# The polynomial-system ensemble: Roessler trajectories at K=300 digits,
+# N=90, from seeded states x0 + uniform [-1, 1]^3 (float64, exact)
+POLY_ENSEMBLE = dict(system="rossler", K=300, N=90, count=64, nsteps=100, seed=5)
+
+
+def poly_states(seed: int, count: int, system: str = "rossler") -> List[Tuple[str, ...]]:
+    """`count` initial states of `system`: its base state plus float64
+    offsets uniform in [-1, 1], as exact rational strings."""
+    from fractions import Fraction
+    rng = np.random.default_rng(seed)
+    base = POLY_X0[system]
+    d = rng.uniform(-1.0, 1.0, (count, len(base)))
+    out = []
+    for t in range(count):
+        row = []
+        for b, x in zip(base, d[t]):
+            q = Fraction(b) + Fraction(float(x))
+            row.append(f"{q.numerator}/{q.denominator}")
+        out.append(tuple(row))
+    return out
