@@ -243,6 +243,59 @@ const char *mpts_strerror(int status);
 /* Text of the last error recorded on this context ("" if none). */
 const char *mpts_last_error(const mpts_ctx *ctx);
 
+/* ---- Polynomial vector fields of degree at most two ----
+ *
+ * The paper notes (Section 2, the paragraph on automatic differentiation,
+ * and Section 6) that the recursion of equation (3) extends to any
+ * right-hand side built from sums and products: each product term gives a
+ * Cauchy-product sum.  A system here is
+ *   dx_v/dt = c_v + sum_u A_vu x_u + sum_{u<=w} B_vuw x_u x_w,  v < nvar <= 4,
+ * given as terms coef * x_u * x_w of equation eq (u = w = -1: the constant
+ * c_eq; w = -1: a linear term).  Per index i: S_uw = sum_k x_{u,i-k} x_{w,k}
+ * rounded once for each distinct pair; x_{v,i+1} = ([i=0] c_v + sum A x_{u,i}
+ * + sum B S_uw) / (i+1) rounded once (exact numerator); the step is
+ * equation (2) by Horner's rule, one rounding per step; every coefficient
+ * and tau rounded once to p bits.  With the Lorenz terms this is exactly the
+ * Lorenz recursion above.
+ *
+ * Limits (MPTS_EUNSUPPORTED beyond them): at most 5 distinct product pairs,
+ * at most one constant term per equation, per equation at most 4 terms
+ * whose coefficient is not +-1 plus 2 whose coefficient is +-1 (further
+ * +-1 terms count as the former), rows of at most 1024 words (L up to about
+ * 800 limbs), and the LDS of one compute unit (160 KB; about L = 300 at
+ * N = 600).  One workgroup integrates one trajectory. */
+typedef struct mpts_poly mpts_poly;
+
+typedef struct {
+  int32_t eq, u, w;   /* equation; variables (-1: absent) */
+  const char *coef;   /* exact decimal or rational string */
+} mpts_poly_term;
+
+/* nvar variables, nterms terms (caller-owned, read during the call), L
+ * limbs (p = 32 L), order N, step tau (string).  Errors: MPTS_EINVAL (bad
+ * term, index or string), MPTS_EUNSUPPORTED (limits above). */
+int mpts_poly_create(int32_t nvar, const mpts_poly_term *terms, int32_t nterms, int32_t L,
+                     int32_t N, const char *tau, mpts_poly **out);
+void mpts_poly_destroy(mpts_poly *ctx);
+
+/* Exact parse of a decimal or rational string, one rounding to p bits. */
+int mpts_poly_bf_from_str(const mpts_poly *ctx, const char *s, mpts_bf *out);
+
+/* `nsteps` steps of `count` trajectories in one launch: x0 and x_out hold
+ * count * nvar big-floats (trajectory-major, host, L limbs each).
+ * Synchronises `stream`; allocates and frees its device memory.
+ * MPTS_ERANGE: an exact sum did not fit the device window (outputs then
+ * undefined); MPTS_EHIP: a HIP error. */
+int mpts_poly_integrate(mpts_poly *ctx, int32_t count, const mpts_bf *x0, int64_t nsteps,
+                        mpts_bf *x_out, void *stream);
+
+/* The Taylor coefficients x_{v,i}, i = 0..N, of one step from x0 (nvar
+ * values): coefs holds nvar * (N + 1) big-floats, variable-major. */
+int mpts_poly_coefficients(mpts_poly *ctx, const mpts_bf *x0, mpts_bf *coefs, void *stream);
+
+/* Text of the last error of a polynomial context ("" if none). */
+const char *mpts_poly_last_error(const mpts_poly *ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -86,6 +86,33 @@ struct Inst {
   unsigned long long *prof;  // per-phase wall-clock ticks (null: not recorded)
 };
 
+// A trajectory of a polynomial vector field of degree at most two:
+//   dx_v/dt = c_v + sum_u A_vu x_u + sum_{u <= w} B_vuw x_u x_w,  v < V.
+// Operands are encoded o < V: the row x_{o,i} of the current index, o >= V:
+// the rounded Cauchy sum S_{o-V} of the pair (pu, pw).  Equation v's
+// numerator is sum_j const[cp[v][j]] * operand(op[v][j]) (np[v] products,
+// one frame) plus na[v] operands with coefficient asg = +-1, plus (index 0
+// only) the constant row cc[v] (-1: none).
+constexpr int PMAXV = 4, PMAXQ = NFR, PMAXP = 4, PMAXA = 3;
+struct PolyInst {
+  int L, N, nd, RS, WB, CM, V, Q;
+  int tau_n, tau_d, tau_m0, tau_m1, tau_e;  // rational step size (tau_d > 0), as in Inst
+  int ctau;                                 // constant row of tau
+  int nconst;
+  int maxn;                                 // bytes of the per-term offset tables
+  long long nsteps;
+  int32_t *rows;    // [V][N+1][RS]
+  int32_t *sums;    // [Q][RS]
+  int32_t *consts;  // [nconst][RS] (written by the kernel from cnorm)
+  int32_t *cnorm;   // [nconst][L+2] normalised constants
+  int32_t *state;   // [V][L+2] normalised state, in and out
+  int32_t *coefs;   // [V][N+1][L+2] normalised coefficients of the first step, or null
+  uint32_t *err;    // error word (bits as in the Lorenz kernels)
+  int pu[PMAXQ], pw[PMAXQ];
+  int np[PMAXV], cp[PMAXV][PMAXP], op[PMAXV][PMAXP];
+  int na[PMAXV], asg[PMAXV][PMAXA], ao[PMAXV][PMAXA], cc[PMAXV];
+};
+
 // phases timed when Inst::prof is set (leader slots 0..15, one follower 16..31)
 enum { PH_SETUP = 0, PH_ACCUM, PH_FLUSH, PH_WAIT, PH_FINAL, PH_CLEAR, PH_HORNER, PH_STEP0,
        PH_EBUILD, PH_ESETUP = 10, PH_NPHASE = 16 };

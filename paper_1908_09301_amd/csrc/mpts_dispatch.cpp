@@ -27,6 +27,16 @@ hipError_t launch_adj(const Inst *d_insts, const int *d_wg_inst, int nwg, int CM
   }
 }
 
+hipError_t launch_poly(const PolyInst *d_insts, int count, int CM, size_t lds, hipStream_t s) {
+  switch (CM) {
+    case 4: return cm4::launch_poly(d_insts, count, lds, s);
+    case 8: return cm8::launch_poly(d_insts, count, lds, s);
+    case 16: return cm16::launch_poly(d_insts, count, lds, s);
+    case 32: return cm32::launch_poly(d_insts, count, lds, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t set_kernel_lds(int CM, size_t lds, bool adjoint) {
   switch (CM) {
     case 4: return cm4::set_lds(lds, adjoint);

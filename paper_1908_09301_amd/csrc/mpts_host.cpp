@@ -470,11 +470,15 @@ int nv_to_bf(const mpts_ctx *c, const int32_t *nv, mpts_bf *b) {
 // integers and one short division instead of a p x p-bit product.  Leaves
 // tau_d = 0 (the full product) for other step sizes and under
 // MPTS_TAU=product.
-void tau_rational(const Rational &q, const std::vector<int32_t> &nv, int L, mpts_ctx *c) {
-  c->tau_d = 0;
+struct TauRat {
+  int n = 0, d = 0, m0 = 0, m1 = 0, e = 0;  // d = 0: the full product
+};
+
+TauRat tau_rational(const Rational &q, const std::vector<int32_t> &nv, int L) {
+  TauRat t;
   const char *env = getenv("MPTS_TAU");
-  if (env && strcmp(env, "product") == 0) return;
-  if (nv[0] == 0 || q.num.size() > 2 || q.den.size() > 2) return;
+  if (env && strcmp(env, "product") == 0) return t;
+  if (nv[0] == 0 || q.num.size() > 2 || q.den.size() > 2) return t;
   auto u64 = [](const Big &a) {
     uint64_t v = 0;
     for (size_t i = a.size(); i-- > 0;) v = (v << 32) | a[i];
@@ -485,7 +489,7 @@ void tau_rational(const Rational &q, const std::vector<int32_t> &nv, int L, mpts
   n /= g;
   d /= g;
   const long long E = nv[1];
-  if (n == 0 || n >= (1u << 27) || d == 0 || d >= (1u << 13) || E > 0) return;
+  if (n == 0 || n >= (1u << 27) || d == 0 || d >= (1u << 13) || E > 0) return t;
   Big M(nv.begin() + 2, nv.begin() + 2 + L);
   trim(M);
   Big dM = M;
@@ -501,15 +505,16 @@ void tau_rational(const Rational &q, const std::vector<int32_t> &nv, int L, mpts
     sub_in(r, dM);
     rs = -1;
   }
-  if (bitlen(r) > 31) return;
+  if (bitlen(r) > 31) return t;
   const long long eE = E >= 0 ? E / DBITS : -((-E + DBITS - 1) / DBITS);
   const int tE = (int)(E - eE * DBITS);
   const long long m = (long long)nv[0] * rs * (long long)(r.empty() ? 0u : r[0]) * (1LL << tE);
-  c->tau_n = nv[0] * (int)n;
-  c->tau_d = (int)d;
-  c->tau_m0 = (int)(m & (long long)DMASK);
-  c->tau_m1 = (int)(m >> DBITS);
-  c->tau_e = (int)eE;
+  t.n = nv[0] * (int)n;
+  t.d = (int)d;
+  t.m0 = (int)(m & (long long)DMASK);
+  t.m1 = (int)(m >> DBITS);
+  t.e = (int)eE;
+  return t;
 }
 
 int make_ctx(const char *sigma, const char *R, const char *b, int L, int N, const char *tau,
@@ -564,7 +569,12 @@ int make_ctx(const char *sigma, const char *R, const char *b, int L, int N, cons
   put(C_NB, nv);
   round_rational(qt, 0, L, nv);
   put(C_TAU, nv);
-  tau_rational(qt, nv, L, c);
+  const TauRat tr = tau_rational(qt, nv, L);
+  c->tau_n = tr.n;
+  c->tau_d = tr.d;
+  c->tau_m0 = tr.m0;
+  c->tau_m1 = tr.m1;
+  c->tau_e = tr.e;
   Rational one;
   one.num = Big{1u};
   one.den = Big{1u};
@@ -1160,6 +1170,286 @@ int integrate_fits(mpts_ctx *c, int64_t nsteps, size_t limit) {
 }  // namespace mpts
 
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Polynomial vector fields of degree at most two (k_poly).
+
+struct mpts_poly {
+  int V = 0, L = 0, N = 0, nd = 0, RS = 0, WB = 0, CM = 0, Q = 0, nconst = 0, maxn = 0;
+  size_t lds = 0;
+  PolyInst proto;           // every field but the pointers
+  std::vector<int32_t> cn;  // nconst x (L+2) normalised constants
+  std::string err;
+};
+
+namespace {
+
+int poly_err(mpts_poly *c, int code, const std::string &msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+bool rational_is_unit(const Rational &q) {
+  Big n = q.num, d = q.den;
+  trim(n);
+  trim(d);
+  return n.size() == 1 && n[0] == 1u && d.size() == 1 && d[0] == 1u;
+}
+
+int make_poly(int32_t nvar, const mpts_poly_term *terms, int32_t nterms, int32_t L, int32_t N,
+              const char *tau, mpts_poly **out) {
+  if (!out) return MPTS_EINVAL;
+  *out = nullptr;
+  if (nvar < 1 || nterms < 0 || (nterms > 0 && !terms) || L < 1 || L > 1024 || N < 1 ||
+      N > 8192 || !tau)
+    return MPTS_EINVAL;
+  if (nvar > PMAXV) return MPTS_EUNSUPPORTED;
+  Rational qt;
+  if (!parse_number(tau, qt)) return MPTS_EINVAL;
+  mpts_poly *c = new mpts_poly();
+  memset(&c->proto, 0, sizeof(c->proto));
+  PolyInst &P = c->proto;
+  c->V = nvar;
+  c->L = L;
+  c->N = N;
+  c->nd = digits_per_row(L);
+  c->RS = row_stride(c->nd);
+  c->WB = frame_width(c->nd);
+  c->CM = choose_cm(c->nd);
+  // the Horner addend prefetch holds rows of at most 1024 words
+  if (c->CM < 0 || c->RS > 1024) {
+    delete c;
+    return MPTS_EUNSUPPORTED;
+  }
+  std::vector<std::vector<int32_t>> consts;
+  std::vector<int32_t> nv;
+  for (int v = 0; v < nvar; ++v) P.cc[v] = -1;
+  // product pairs first (their operand codes follow the variables)
+  std::vector<std::pair<int, int>> pairs;
+  for (int t = 0; t < nterms; ++t) {
+    const mpts_poly_term &m = terms[t];
+    if (m.eq < 0 || m.eq >= nvar || m.u < -1 || m.u >= nvar || m.w < -1 || m.w >= nvar ||
+        (m.u < 0 && m.w >= 0) || !m.coef) {
+      delete c;
+      return MPTS_EINVAL;
+    }
+    if (m.w >= 0) {
+      const std::pair<int, int> q(std::min(m.u, m.w), std::max(m.u, m.w));
+      if (std::find(pairs.begin(), pairs.end(), q) == pairs.end()) pairs.push_back(q);
+    }
+  }
+  if ((int)pairs.size() > PMAXQ) {
+    delete c;
+    return MPTS_EUNSUPPORTED;
+  }
+  c->Q = (int)pairs.size();
+  for (int q = 0; q < c->Q; ++q) {
+    P.pu[q] = pairs[q].first;
+    P.pw[q] = pairs[q].second;
+  }
+  for (int t = 0; t < nterms; ++t) {
+    const mpts_poly_term &m = terms[t];
+    Rational q;
+    if (!parse_number(m.coef, q)) {
+      delete c;
+      return MPTS_EINVAL;
+    }
+    if (q.num.empty()) continue;  // a zero coefficient adds nothing
+    round_rational(q, 0, L, nv);
+    const int v = m.eq;
+    if (m.u < 0) {
+      if (P.cc[v] >= 0) {  // one constant term per equation
+        delete c;
+        return MPTS_EUNSUPPORTED;
+      }
+      P.cc[v] = (int)consts.size();
+      consts.push_back(nv);
+      continue;
+    }
+    int opnd = m.u;
+    if (m.w >= 0) {
+      const std::pair<int, int> pq(std::min(m.u, m.w), std::max(m.u, m.w));
+      opnd = nvar + (int)(std::find(pairs.begin(), pairs.end(), pq) - pairs.begin());
+    }
+    // coefficient +-1: a row addend (the constant term of index 0 keeps one slot)
+    if (rational_is_unit(q) && P.na[v] < PMAXA - 1) {
+      P.asg[v][P.na[v]] = q.neg ? -1 : 1;
+      P.ao[v][P.na[v]] = opnd;
+      ++P.na[v];
+      continue;
+    }
+    if (P.np[v] >= PMAXP) {
+      delete c;
+      return MPTS_EUNSUPPORTED;
+    }
+    P.cp[v][P.np[v]] = (int)consts.size();
+    P.op[v][P.np[v]] = opnd;
+    ++P.np[v];
+    consts.push_back(nv);
+  }
+  round_rational(qt, 0, L, nv);
+  const TauRat tr = tau_rational(qt, nv, L);
+  P.ctau = (int)consts.size();
+  consts.push_back(nv);
+  c->nconst = (int)consts.size();
+  c->cn.assign((size_t)c->nconst * (L + 2), 0);
+  for (int k = 0; k < c->nconst; ++k)
+    std::copy(consts[k].begin(), consts[k].end(), c->cn.begin() + (size_t)k * (L + 2));
+  c->maxn = std::max(c->Q * ((N + 16) & ~15), nvar * PMAXP * 16);
+  c->lds = poly_lds_bytes(nvar, c->Q, c->RS, c->WB, c->CM, c->maxn);
+  if (c->lds > kLdsPerCU) {
+    delete c;
+    return MPTS_EUNSUPPORTED;
+  }
+  P.L = L;
+  P.N = N;
+  P.nd = c->nd;
+  P.RS = c->RS;
+  P.WB = c->WB;
+  P.CM = c->CM;
+  P.V = nvar;
+  P.Q = c->Q;
+  P.tau_n = tr.n;
+  P.tau_d = tr.d;
+  P.tau_m0 = tr.m0;
+  P.tau_m1 = tr.m1;
+  P.tau_e = tr.e;
+  P.nconst = c->nconst;
+  P.maxn = c->maxn;
+  *out = c;
+  return MPTS_OK;
+}
+
+int poly_bf_to_nv(int L, const mpts_bf &b, int32_t *nv) {
+  if (b.sign == 0) {
+    for (int j = 0; j < L + 2; ++j) nv[j] = 0;
+    return MPTS_OK;
+  }
+  if (!b.limbs || (b.sign != 1 && b.sign != -1) || !(b.limbs[L - 1] & 0x80000000u))
+    return MPTS_EINVAL;
+  nv[0] = b.sign;
+  nv[1] = b.exp;
+  for (int j = 0; j < L; ++j) nv[2 + j] = (int32_t)b.limbs[j];
+  return MPTS_OK;
+}
+
+int poly_nv_to_bf(int L, const int32_t *nv, mpts_bf *b) {
+  if (!b->limbs) return MPTS_EINVAL;
+  b->sign = nv[0];
+  b->exp = nv[0] ? nv[1] : 0;
+  for (int j = 0; j < L; ++j) b->limbs[j] = (uint32_t)nv[2 + j];
+  return MPTS_OK;
+}
+
+// Device bytes of one trajectory's region (rows, sums, constants, state,
+// coefficients, error word), 256-byte aligned parts.
+struct PolyLayout {
+  size_t rows, sums, consts, cnorm, state, coefs, err, total;
+};
+
+PolyLayout poly_layout(const mpts_poly *c, bool coefs) {
+  PolyLayout l;
+  size_t o = 0;
+  auto put = [&](size_t bytes) {
+    size_t at = o;
+    o = al(o + bytes);
+    return at;
+  };
+  l.rows = put((size_t)c->V * (c->N + 1) * c->RS * 4);
+  l.sums = put((size_t)std::max(c->Q, 1) * c->RS * 4);
+  l.consts = put((size_t)c->nconst * c->RS * 4);
+  l.cnorm = put((size_t)c->nconst * (c->L + 2) * 4);
+  l.state = put((size_t)c->V * (c->L + 2) * 4);
+  l.coefs = put(coefs ? (size_t)c->V * (c->N + 1) * (c->L + 2) * 4 : 0);
+  l.err = put(4);
+  l.total = o;
+  return l;
+}
+
+int poly_run(mpts_poly *c, int32_t count, const mpts_bf *x0, int64_t nsteps, mpts_bf *x_out,
+             mpts_bf *coefs, void *stream) {
+  if (!c || count < 1 || !x0 || !x_out || nsteps < 0 || (coefs && count != 1))
+    return poly_err(c, MPTS_EINVAL, "bad argument");
+  hipStream_t s = (hipStream_t)stream;
+  const int V = c->V, L = c->L;
+  const PolyLayout l = poly_layout(c, coefs != nullptr);
+  const size_t region = l.total;
+  const size_t ibytes = al((size_t)count * sizeof(PolyInst));
+  const size_t total = ibytes + (size_t)count * region;
+  // host image: descriptors, and each region's constants and state
+  std::vector<PolyInst> insts((size_t)count, c->proto);
+  std::vector<int32_t> st((size_t)V * (L + 2));
+  char *base = nullptr;
+  hipError_t e = hipMalloc((void **)&base, total);
+  if (e != hipSuccess) return poly_err(c, MPTS_EHIP, std::string("allocate: ") + hipGetErrorString(e));
+  auto fail = [&](int code, const std::string &msg) {
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(base);
+    return poly_err(c, code, msg);
+  };
+  e = launch_clear(base, total, s);
+  if (e != hipSuccess) return fail(MPTS_EHIP, "clear");
+  for (int t = 0; t < count; ++t) {
+    char *rb = base + ibytes + (size_t)t * region;
+    PolyInst &P = insts[t];
+    P.nsteps = nsteps;
+    P.rows = (int32_t *)(rb + l.rows);
+    P.sums = (int32_t *)(rb + l.sums);
+    P.consts = (int32_t *)(rb + l.consts);
+    P.cnorm = (int32_t *)(rb + l.cnorm);
+    P.state = (int32_t *)(rb + l.state);
+    P.coefs = coefs ? (int32_t *)(rb + l.coefs) : nullptr;
+    P.err = (uint32_t *)(rb + l.err);
+    for (int v = 0; v < V; ++v)
+      if (poly_bf_to_nv(L, x0[(size_t)t * V + v], st.data() + (size_t)v * (L + 2)) != MPTS_OK)
+        return fail(MPTS_EINVAL, "bad initial state");
+    e = hipMemcpyAsync(rb + l.cnorm, c->cn.data(), c->cn.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(rb + l.state, st.data(), st.size() * 4, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return fail(MPTS_EHIP, "copy inputs");
+    // the copies read st: finish them before it is refilled
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(MPTS_EHIP, "synchronize");
+  }
+  e = hipMemcpyAsync(base, insts.data(), insts.size() * sizeof(PolyInst), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return fail(MPTS_EHIP, "copy descriptors");
+  e = launch_poly((const PolyInst *)base, count, c->CM, c->lds, s);
+  if (e != hipSuccess) return fail(MPTS_EHIP, std::string("launch: ") + hipGetErrorString(e));
+  std::vector<uint32_t> errs((size_t)count);
+  std::vector<int32_t> outs((size_t)count * V * (L + 2));
+  for (int t = 0; t < count; ++t) {
+    char *rb = base + ibytes + (size_t)t * region;
+    e = hipMemcpyAsync(&errs[t], rb + l.err, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(outs.data() + (size_t)t * V * (L + 2), rb + l.state,
+                         (size_t)V * (L + 2) * 4, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return fail(MPTS_EHIP, "copy results");
+  }
+  std::vector<int32_t> cf;
+  if (coefs) {
+    cf.resize((size_t)V * (c->N + 1) * (L + 2));
+    e = hipMemcpyAsync(cf.data(), base + ibytes + l.coefs, cf.size() * 4, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return fail(MPTS_EHIP, "copy coefficients");
+  }
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(MPTS_EHIP, std::string("synchronize: ") + hipGetErrorString(e));
+  (void)hipFree(base);
+  for (int t = 0; t < count; ++t) {
+    const uint32_t w = errs[t];
+    if (w & 8u) return poly_err(c, MPTS_EUNSUPPORTED, "per-term offset table overflow");
+    if (w & 3u) return poly_err(c, MPTS_ERANGE, "exact sum outside the device window");
+  }
+  for (size_t j = 0; j < (size_t)count * V; ++j)
+    if (poly_nv_to_bf(L, outs.data() + j * (L + 2), &x_out[j]) != MPTS_OK)
+      return poly_err(c, MPTS_EINVAL, "output without limb storage");
+  if (coefs)
+    for (size_t j = 0; j < (size_t)V * (c->N + 1); ++j)
+      if (poly_nv_to_bf(L, cf.data() + j * (L + 2), &coefs[j]) != MPTS_OK)
+        return poly_err(c, MPTS_EINVAL, "output without limb storage");
+  return MPTS_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int mpts_create(const char *sigma, const char *R, const char *b, int32_t K_digits, int32_t N,
@@ -1794,5 +2084,36 @@ const char *mpts_strerror(int status) {
 }
 
 const char *mpts_last_error(const mpts_ctx *c) { return c ? c->err.c_str() : ""; }
+
+int mpts_poly_create(int32_t nvar, const mpts_poly_term *terms, int32_t nterms, int32_t L,
+                     int32_t N, const char *tau, mpts_poly **out) {
+  return make_poly(nvar, terms, nterms, L, N, tau, out);
+}
+
+void mpts_poly_destroy(mpts_poly *ctx) { delete ctx; }
+
+int mpts_poly_bf_from_str(const mpts_poly *c, const char *s, mpts_bf *out) {
+  if (!c || !out || !s) return MPTS_EINVAL;
+  Rational q;
+  if (!parse_number(s, q)) return MPTS_EINVAL;
+  std::vector<int32_t> nv;
+  round_rational(q, 0, c->L, nv);
+  return poly_nv_to_bf(c->L, nv.data(), out);
+}
+
+int mpts_poly_integrate(mpts_poly *ctx, int32_t count, const mpts_bf *x0, int64_t nsteps,
+                        mpts_bf *x_out, void *stream) {
+  return poly_run(ctx, count, x0, nsteps, x_out, nullptr, stream);
+}
+
+int mpts_poly_coefficients(mpts_poly *ctx, const mpts_bf *x0, mpts_bf *coefs, void *stream) {
+  if (!ctx || !coefs) return MPTS_EINVAL;
+  std::vector<uint32_t> store((size_t)ctx->V * ctx->L);
+  std::vector<mpts_bf> out((size_t)ctx->V);
+  for (int v = 0; v < ctx->V; ++v) out[v].limbs = store.data() + (size_t)v * ctx->L;
+  return poly_run(ctx, 1, x0, 1, out.data(), coefs, stream);
+}
+
+const char *mpts_poly_last_error(const mpts_poly *c) { return c ? c->err.c_str() : ""; }
 
 }  // extern "C"

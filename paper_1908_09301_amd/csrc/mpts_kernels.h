@@ -13,6 +13,7 @@ namespace mpts {
                         hipStream_t s, bool cooperative);                                       \
   hipError_t launch_adj(const Inst *d_insts, const int *d_wg_inst, int nwg, size_t lds,         \
                         hipStream_t s);                                                         \
+  hipError_t launch_poly(const PolyInst *d_insts, int count, size_t lds, hipStream_t s);       \
   hipError_t set_lds(size_t lds, bool adjoint);                                                 \
   hipError_t occupancy(int *nb, size_t lds, bool adjoint);                                      \
   }
@@ -35,6 +36,11 @@ hipError_t launch_run(const Inst *d_insts, const int *d_wg_inst, int nwg, int CM
 // Cooperative launch of the adjoint kernel (reverse sweep over checkpoints).
 hipError_t launch_adj(const Inst *d_insts, const int *d_wg_inst, int nwg, int CM, size_t lds,
                       hipStream_t s);
+
+// One workgroup per trajectory of a polynomial vector field (k_poly).
+hipError_t launch_poly(const PolyInst *d_insts, int count, int CM, size_t lds, hipStream_t s);
+// Bytes of dynamic LDS one workgroup of k_poly needs.
+size_t poly_lds_bytes(int V, int Q, int RS, int WB, int CM, int maxn);
 
 // Allow the forward (or adjoint) kernel instance for CM the given dynamic LDS size.
 hipError_t set_kernel_lds(int CM, size_t lds, bool adjoint);

@@ -1707,6 +1707,274 @@ __global__ void __launch_bounds__(WGS) k_run(const Inst *__restrict__ insts,
 }
 
 // ---------------------------------------------------------------------------
+// Polynomial vector fields of degree at most two.  Every product term of a
+// right-hand side contributes a Cauchy-product sum of the kind equation (3)
+// holds for the Lorenz system (Section 2, the paragraph on automatic
+// differentiation): with x_{v,0} the state, for i = 0..N-1
+//   S_q       = round(sum_{k=0}^{i} x_{u_q,i-k} x_{w_q,k})            (each pair q)
+//   x_{v,i+1} = round(([i=0] c_v + sum A_vu x_{u,i} + sum B_vq S_q) / (i+1))
+// then the Horner sums of equation (2).  One workgroup integrates one
+// trajectory (a launch runs a batch), with the frames of an index in LDS:
+// the Cauchy frames of all pairs in one pass of the product tiles, each
+// rounded by one wavefront, then the numerator frames (constants times
+// rows) in a second pass, each divided and rounded by one wavefront.
+
+// LDS carve of one workgroup of k_poly.
+struct PolyCarve {
+  long long *lf;     // NFR * WB frame columns
+  FrameSrc *fs;      // NFR
+  FrameD *fd;        // NFR
+  int *red;          // 2 NFR (frame_setup's reduction)
+  int *span;         // 2 NFR
+  int8_t *offs;      // maxn bytes: per-term offset tables
+  long long *scr;    // 4 wavefronts x 64 CM words of task scratch
+  int32_t *cur;      // V rows: x_{v,i} (the Horner accumulators after the index loop)
+  int32_t *srow;     // Q rows: S_q
+  int32_t *orow;     // V rows: x_{v,i+1}
+  int32_t *crow;     // V rows: the constant term c_v (zero row: none)
+  int32_t *hb;       // 2 V rows: Horner addends; then the tau row
+};
+
+__host__ __device__ inline size_t poly_carve(int V, int Q, int RS, int WB, int CM, int maxn,
+                                             unsigned char *base, PolyCarve *cv) {
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += (bytes + 15) & ~(size_t)15;
+    return base ? base + at : nullptr;
+  };
+  PolyCarve c;
+  c.lf = (long long *)take((size_t)NFR * WB * 8);
+  c.fs = (FrameSrc *)take(sizeof(FrameSrc) * NFR);
+  c.fd = (FrameD *)take(sizeof(FrameD) * NFR);
+  c.red = (int *)take(2 * NFR * 4);
+  c.span = (int *)take(2 * NFR * 4);
+  c.offs = (int8_t *)take((size_t)maxn);
+  c.scr = (long long *)take((size_t)4 * 64 * CM * 8);
+  c.cur = (int32_t *)take((size_t)V * RS * 4);
+  c.srow = (int32_t *)take((size_t)(Q > 0 ? Q : 1) * RS * 4);
+  c.orow = (int32_t *)take((size_t)V * RS * 4);
+  c.crow = (int32_t *)take((size_t)V * RS * 4);
+  c.hb = (int32_t *)take((size_t)(2 * V + 1) * RS * 4);
+  if (cv) *cv = c;
+  return o;
+}
+
+__device__ __forceinline__ int32_t *poly_row(const PolyInst &P, int v, int i) {
+  return P.rows + ((long long)v * (P.N + 1) + i) * P.RS;
+}
+
+// Operand o of index i in global memory (rows, or the published sums).
+__device__ __forceinline__ const int32_t *poly_opnd(const PolyInst &P, int o, int i) {
+  return o < P.V ? poly_row(P, o, i) : P.sums + (long long)(o - P.V) * P.RS;
+}
+
+// Copy a row (RS words) between LDS and global memory by `nthr` threads.
+__device__ __forceinline__ void poly_copy(const int32_t *src, int32_t *dst, int RS, int t, int nthr) {
+  for (int w = t; w < RS; w += nthr) dst[w] = src[w];
+}
+
+// Round the frame lf[f] (descriptor fd[f], row addends ad) into the LDS row
+// out (div: divide by it first; 0: none) and clear the frame's columns.
+// Single wavefront.
+template <int CM>
+__device__ __forceinline__ void poly_task(const PolyInst &P, const PolyCarve &cv, int f,
+                                          const RowAdd *ad, int nad, int div, int32_t *out) {
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  int32_t *scratch = (int32_t *)(cv.scr + (size_t)wave * 64 * CM);
+  const FrameD d = lds_get(cv.fd + f);
+  if (!sum_to_row<CM>(cv.lf + (size_t)f * P.WB, false, &d, P.nd, ad, nad, div, P.L, P.RS, scratch,
+                      out, P.err) &&
+      lane == 0)
+    atomicOr(P.err, 2u);
+  const int ncol = d.nz ? frame_cols(d, P.nd) : 0;
+  for (int c = lane; c < ncol; c += 64) ((l_i64 *)cv.lf)[(size_t)f * P.WB + c] = 0;
+}
+
+template <int CM>
+__global__ void __launch_bounds__(WGS) k_poly(const PolyInst *__restrict__ insts) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const PolyInst P = insts[blockIdx.x];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int L = P.L, N = P.N, nd = P.nd, RS = P.RS, WB = P.WB, V = P.V, Q = P.Q;
+  PolyCarve cv;
+  (void)poly_carve(V, Q, RS, WB, CM, P.maxn, smem, &cv);
+  for (int j = tid; j < NFR * WB; j += WGS) cv.lf[j] = 0;
+  red_reset(cv.red);
+  // constants as rows (global), the constant terms and the state as LDS rows
+  for (int c = 0; c < P.nconst; ++c)
+    write_row(P.cnorm + (size_t)c * (L + 2), L, nd, RS, P.consts + (size_t)c * RS, false, tid, WGS);
+  for (int v = 0; v < V; ++v) {
+    if (P.cc[v] >= 0)
+      write_row(P.cnorm + (size_t)P.cc[v] * (L + 2), L, nd, RS, cv.crow + (size_t)v * RS, false,
+                tid, WGS);
+    else
+      for (int w = tid; w < RS; w += WGS) cv.crow[(size_t)v * RS + w] = 0;
+    write_row(P.state + (size_t)v * (L + 2), L, nd, RS, cv.cur + (size_t)v * RS, false, tid, WGS);
+  }
+  __syncthreads();
+  const TauQ tq{P.tau_n, P.tau_m0, P.tau_m1, P.tau_e, P.tau_d};
+  auto nomark = [](int) {};
+  for (long long step = 0; step < P.nsteps; ++step) {
+    // the state rows x_{v,0}
+    for (int w = tid; w < V * RS; w += WGS) {
+      const int v = w / RS, k = w - v * RS;
+      poly_row(P, v, 0)[k] = cv.cur[w];
+    }
+    if (P.coefs && step == 0 && wave < V) {
+      int32_t *scratch = (int32_t *)(cv.scr + (size_t)wave * 64 * CM);
+      int32_t *nv = scratch + 64 * CM;
+      row_to_norm<CM>(cv.cur + (size_t)wave * RS, L, nd, scratch, nv);
+      copy_norm(nv, P.coefs + (size_t)wave * (N + 1) * (L + 2), L, false, lane, 64);
+    }
+    wait_vmem();
+    __syncthreads();
+    for (int i = 0; i < N; ++i) {
+      // Cauchy sums of the pairs
+      if (Q > 0) {
+        if (tid == 0)
+          for (int q = 0; q < Q; ++q)
+            lds_put(cv.fs + q, mk_frame1(mk_part(PK_CAUCHY, i + 1, i, poly_row(P, P.pu[q], 0),
+                                                 poly_row(P, P.pw[q], 0))));
+        __syncthreads();
+        frame_setup(cv.fs, cv.fd, Q, nd, RS, cv.red, cv.offs, P.maxn, P.err);
+        frames_accumulate(cv.fs, cv.fd, Q, nd, RS, WB, cv.lf, 0, 1, cv.span);
+        __syncthreads();
+        for (int q = wave; q < Q; q += 4) {
+          poly_task<CM>(P, cv, q, nullptr, 0, 0, cv.srow + (size_t)q * RS);
+          poly_copy(cv.srow + (size_t)q * RS, P.sums + (size_t)q * RS, RS, lane, 64);
+        }
+        wait_vmem();
+        __syncthreads();
+      }
+      // numerators: constants times operands in one frame per equation
+      if (tid == 0)
+        for (int v = 0; v < V; ++v) {
+          FrameSrc f;
+          FramePart pt[PMAXP];
+          for (int j = 0; j < PMAXP; ++j)
+            pt[j] = j < P.np[v] ? mk_part(PK_ONE, 1, 0, P.consts + (size_t)P.cp[v][j] * RS,
+                                          poly_opnd(P, P.op[v][j], i))
+                                : mk_part(PK_ONE, 0, 0, P.consts, P.consts);
+          f = mk_frame4(pt[0], pt[1], pt[2], pt[3]);
+          f.nparts = P.np[v];
+          f.n = P.np[v];
+          lds_put(cv.fs + v, f);
+        }
+      __syncthreads();
+      frame_setup(cv.fs, cv.fd, V, nd, RS, cv.red, cv.offs, P.maxn, P.err);
+      frames_accumulate(cv.fs, cv.fd, V, nd, RS, WB, cv.lf, 0, 1, cv.span);
+      __syncthreads();
+      for (int v = wave; v < V; v += 4) {
+        RowAdd ad[PMAXA];
+        int nad = 0;
+        for (int k = 0; k < P.na[v]; ++k) {
+          const int o = P.ao[v][k];
+          ad[nad++] = RowAdd{o < V ? cv.cur + (size_t)o * RS : cv.srow + (size_t)(o - V) * RS,
+                             P.asg[v][k], 1};
+        }
+        if (i == 0 && P.cc[v] >= 0 && nad < PMAXA) ad[nad++] = RowAdd{cv.crow + (size_t)v * RS, 1, 1};
+        poly_task<CM>(P, cv, v, ad, nad, i + 1, cv.orow + (size_t)v * RS);
+      }
+      __syncthreads();
+      // the new rows x_{v,i+1}: global memory and the current rows
+      for (int w = tid; w < V * RS; w += WGS) {
+        const int v = w / RS, k = w - v * RS;
+        const int32_t x = cv.orow[w];
+        poly_row(P, v, i + 1)[k] = x;
+        cv.cur[w] = x;
+      }
+      if (P.coefs && step == 0 && wave < V) {
+        int32_t *scratch = (int32_t *)(cv.scr + (size_t)wave * 64 * CM);
+        int32_t *nv = scratch + 64 * CM;
+        row_to_norm<CM>(cv.orow + (size_t)wave * RS, L, nd, scratch, nv);
+        copy_norm(nv, P.coefs + ((size_t)wave * (N + 1) + i + 1) * (L + 2), L, false, lane, 64);
+      }
+      wait_vmem();
+      __syncthreads();
+    }
+    // Horner (equation (2)): h_v = x_{v,N}; h_v <- round(tau h_v + x_{v,i}), i = N-1..0
+    if (P.tau_d > 0) {
+      // one chain per wavefront, the next addend row loaded while a step runs
+      if (wave < V) {
+        int32_t *h = cv.cur + (size_t)wave * RS;
+        int32_t *hb = cv.hb + (size_t)wave * 2 * RS;
+        int32_t *scratch = (int32_t *)(cv.scr + (size_t)wave * 64 * CM);
+        constexpr int PRE = 16;  // RS <= 64 PRE words per row
+        int32_t pre[PRE];
+        auto load = [&](int idx) {
+          const int32_t *src = poly_row(P, wave, idx);
+#pragma unroll
+          for (int j = 0; j < PRE; ++j) {
+            const int w = lane + 64 * j;
+            pre[j] = w < RS ? src[w] : 0;
+          }
+        };
+        auto store = [&](int32_t *dst) {
+#pragma unroll
+          for (int j = 0; j < PRE; ++j) {
+            const int w = lane + 64 * j;
+            if (w < RS) dst[w] = pre[j];
+          }
+        };
+        if (N > 0) {
+          load(N - 1);
+          store(hb);
+        }
+        for (int it = 0; it < N; ++it) {
+          int32_t *cur_add = hb + (size_t)(it & 1) * RS;
+          if (it + 1 < N) load(N - 2 - it);
+          __builtin_amdgcn_wave_barrier();
+          if (!tau_step_rational<CM>(tq, L, nd, RS, h, cur_add, scratch, P.err, nomark) && lane == 0)
+            atomicOr(P.err, 2u);
+          if (it + 1 < N) store(hb + (size_t)((it + 1) & 1) * RS);
+          __builtin_amdgcn_wave_barrier();
+        }
+      }
+      __syncthreads();
+    } else {
+      int32_t *tau_lds = cv.hb + (size_t)2 * V * RS;
+      for (int w = tid; w < RS; w += WGS) tau_lds[w] = P.consts[(size_t)P.ctau * RS + w];
+      __syncthreads();
+      for (int it = 0; it < N; ++it) {
+        for (int w = tid; w < V * RS; w += WGS) {
+          const int v = w / RS, k = w - v * RS;
+          cv.hb[w] = poly_row(P, v, N - 1 - it)[k];
+        }
+        lds_products(tau_lds, cv.cur, RS, V, nd, WB, cv.lf);
+        __syncthreads();
+        if (wave < V) {
+          int32_t *h = cv.cur + (size_t)wave * RS;
+          const FrameD fdw = single_desc(tau_lds, h, nd);
+          const RowAdd ad{cv.hb + (size_t)wave * RS, 1, 1};
+          int32_t *scratch = (int32_t *)(cv.scr + (size_t)wave * 64 * CM);
+          if (!sum_to_row<CM>(cv.lf + (size_t)wave * WB, false, &fdw, nd, &ad, 1, 0, L, RS, scratch,
+                              h, P.err) &&
+              lane == 0)
+            atomicOr(P.err, 2u);
+          const int ncol = fdw.nz ? frame_cols(fdw, nd) : 0;
+          for (int c = lane; c < ncol; c += 64) ((l_i64 *)cv.lf)[(size_t)wave * WB + c] = 0;
+        }
+        __syncthreads();
+      }
+    }
+  }
+  // the final state, normalised
+  if (wave < V) {
+    int32_t *scratch = (int32_t *)(cv.scr + (size_t)wave * 64 * CM);
+    int32_t *nv = scratch + 64 * CM;
+    row_to_norm<CM>(cv.cur + (size_t)wave * RS, L, nd, scratch, nv);
+    copy_norm(nv, P.state + (size_t)wave * (L + 2), L, false, lane, 64);
+  }
+}
+
+#if MPTS_CM == 4
+size_t poly_lds_bytes(int V, int Q, int RS, int WB, int CM, int maxn) {
+  return poly_carve(V, Q, RS, WB, CM, maxn, nullptr, nullptr);
+}
+#endif
+
+// ---------------------------------------------------------------------------
 // Adjoint: reverse sweep over the steps of a checkpointed forward run.
 //
 // For step n (from the last to the first), with incoming adjoints X, Y, Z of
@@ -1901,6 +2169,15 @@ hipError_t launch_adj(const Inst *d_insts, const int *d_wg_inst, int nwg, size_t
   void *args[] = {(void *)&d_insts, (void *)&d_wg_inst};
   return hipLaunchCooperativeKernel((const void *)kern, dim3(nwg), dim3(WGS), args, (unsigned)lds,
                                     s);
+}
+
+hipError_t launch_poly(const PolyInst *d_insts, int count, size_t lds, hipStream_t s) {
+  auto kern = k_poly<MPTS_CM>;
+  hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(count), dim3(WGS), lds, s, d_insts);
+  return hipGetLastError();
 }
 
 hipError_t set_lds(size_t lds, bool adjoint) {

@@ -39,6 +39,8 @@ SYMBOLS = (
     "mpts_batch_workspace_bytes", "mpts_integrate_batch", "mpts_grad",
     "mpts_grad_batch_workspace_bytes", "mpts_grad_batch", "mpts_release_caches",
     "mpts_probe_rate", "mpts_integrate_dev_noalloc", "mpts_strerror", "mpts_last_error",
+    "mpts_poly_create", "mpts_poly_destroy", "mpts_poly_bf_from_str", "mpts_poly_integrate",
+    "mpts_poly_coefficients", "mpts_poly_last_error",
 )
 
 if not os.path.exists(LIB_PATH):
@@ -94,6 +96,22 @@ _lib.mpts_strerror.argtypes = [_i32]
 _lib.mpts_strerror.restype = ctypes.c_char_p
 _lib.mpts_last_error.argtypes = [_P]
 _lib.mpts_last_error.restype = ctypes.c_char_p
+
+
+class mpts_poly_term(ctypes.Structure):
+    _fields_ = [("eq", ctypes.c_int32), ("u", ctypes.c_int32), ("w", ctypes.c_int32),
+                ("coef", ctypes.c_char_p)]
+
+
+_lib.mpts_poly_create.argtypes = [_i32, ctypes.POINTER(mpts_poly_term), _i32, _i32, _i32,
+                                  ctypes.c_char_p, ctypes.POINTER(_P)]
+_lib.mpts_poly_destroy.argtypes = [_P]
+_lib.mpts_poly_destroy.restype = None
+_lib.mpts_poly_bf_from_str.argtypes = [_P, ctypes.c_char_p, _BFP]
+_lib.mpts_poly_integrate.argtypes = [_P, _i32, _BFP, _i64, _BFP, _P]
+_lib.mpts_poly_coefficients.argtypes = [_P, _BFP, _BFP, _P]
+_lib.mpts_poly_last_error.argtypes = [_P]
+_lib.mpts_poly_last_error.restype = ctypes.c_char_p
 
 
 # Orderly shutdown: at interpreter exit, before the HIP runtime and the
@@ -387,6 +405,76 @@ def _batch_states(problems, outs):
             r.append((int(b.sign), m, int(b.exp)) if b.sign else (0, 0, 0))
         res.append(r)
     return res
+
+
+def _limbs_for_digits(K: int) -> int:
+    """The library's limb count for K decimal digits (from a throwaway
+    context; no device work)."""
+    h = _P()
+    st = _lib.mpts_create(b"10", b"28", b"8/3", K, 1, b"1/100", ctypes.byref(h))
+    if st != MPTS_OK:
+        raise MptsError(st)
+    L = _i32()
+    _lib.mpts_limbs(h, ctypes.byref(L), None, None)
+    _lib.mpts_destroy(h)
+    return L.value
+
+
+class Poly:
+    """A polynomial vector field of degree at most two: `nvar` variables and
+    terms (eq, coef, u, w) meaning coef * x_u * x_w in dx_eq/dt (u, w = -1:
+    absent); order N, step tau, precision K decimal digits or L limbs."""
+
+    def __init__(self, nvar: int, terms, K: Optional[int] = None, N: int = 40,
+                 L: Optional[int] = None, tau: str = "1/100"):
+        if L is None:
+            L = _limbs_for_digits(K)
+        self.nvar, self.L, self.p, self.N = nvar, L, 32 * L, N
+        self._coefs = [_bytes(t[1]) for t in terms]  # kept alive during the call
+        arr = (mpts_poly_term * max(len(terms), 1))()
+        for j, (eq, coef, u, w) in enumerate(terms):
+            arr[j].eq, arr[j].u, arr[j].w, arr[j].coef = eq, u, w, self._coefs[j]
+        h = _P()
+        st = _lib.mpts_poly_create(nvar, arr, len(terms), L, N, _bytes(tau), ctypes.byref(h))
+        if st != MPTS_OK:
+            raise MptsError(st)
+        self._h = h
+
+    def __del__(self, _state=_STATE):
+        h = getattr(self, "_h", None)
+        self._h = None
+        if h and not _state["closed"]:
+            _state["lib"].mpts_poly_destroy(h)
+
+    def _check(self, st: int):
+        if st != MPTS_OK:
+            raise MptsError(st, _lib.mpts_poly_last_error(self._h).decode())
+
+    def from_str(self, s: str) -> Tuple[int, int, int]:
+        a = BFArray(1, self.L)
+        self._check(_lib.mpts_poly_bf_from_str(self._h, _bytes(s), a.ptr()))
+        return a.get(0)
+
+    def integrate(self, x0s, nsteps: int):
+        """`nsteps` steps of every trajectory in x0s (a list of nvar-tuples
+        of (sign, mantissa, exponent)) in one launch."""
+        n = len(x0s)
+        a = BFArray(n * self.nvar, self.L)
+        out = BFArray(n * self.nvar, self.L)
+        for t, x in enumerate(x0s):
+            for v in range(self.nvar):
+                a.set(t * self.nvar + v, x[v])
+        self._check(_lib.mpts_poly_integrate(self._h, n, a.ptr(), nsteps, out.ptr(), _stream()))
+        return [tuple(out.get(t * self.nvar + v) for v in range(self.nvar)) for t in range(n)]
+
+    def coefficients(self, x0):
+        """The Taylor coefficients of one step: nvar lists of N+1 values."""
+        a = BFArray(self.nvar, self.L)
+        for v in range(self.nvar):
+            a.set(v, x0[v])
+        c = BFArray(self.nvar * (self.N + 1), self.L)
+        self._check(_lib.mpts_poly_coefficients(self._h, a.ptr(), c.ptr(), _stream()))
+        return [[c.get(v * (self.N + 1) + i) for i in range(self.N + 1)] for v in range(self.nvar)]
 
 
 def integrate_batch(problems: Sequence[Lorenz], x0s, nsteps: Sequence[int], flags: int = 0):
