@@ -284,6 +284,53 @@ def run_batch(args):
           flush=True)
 
 
+def run_poly(args):
+    """Polynomial vector fields (k_poly, one workgroup per trajectory): the
+    Roessler ensemble (64 trajectories, K=300, N=90) in one launch, and the
+    Lorenz system given as terms against the Lorenz batch path on 16 of the
+    same-size trajectories."""
+    import torch
+    from paper_1908_09301_amd import mpts
+    from workloads import POLY_ENSEMBLE, POLY_SYSTEMS, poly_states
+    E = POLY_ENSEMBLE
+    nvar, terms = POLY_SYSTEMS[E["system"]]
+    p = mpts.Poly(nvar, terms, K=E["K"], N=E["N"])
+    x0s = [[p.from_str(v) for v in x] for x in poly_states(E["seed"], E["count"], E["system"])]
+    n = args.steps
+    p.integrate(x0s, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p.integrate(x0s, n)
+    t = time.perf_counter() - t0
+    # limb MACs of one trajectory step (schoolbook count): the Cauchy sums of
+    # the product pairs, the products of non-unit coefficients, the Horner steps
+    N, L = E["N"], p.L
+    pairs = {(min(u, w), max(u, w)) for (_, _, u, w) in terms if w >= 0}
+    nprod = sum(1 for (_, c, u, _) in terms if u >= 0 and c not in ("1", "-1"))
+    macs = (len(pairs) * N * (N + 1) // 2 + nprod * N + nvar * N) * L * L
+    out = {"metric": "polynomial-system ensemble", "workload": f"{E['system']}_k{E['K']}_n{N}_x{E['count']}",
+           "steps": n, "s": t, "trajectory_steps_per_s": E["count"] * n / t,
+           "ms_per_step": t / n * 1e3, "limb_mac_per_s": E["count"] * n * macs / t,
+           "frac_of_alu_peak": E["count"] * n * macs / t / INT_VALU_PEAK}
+    # the Lorenz terms on k_poly vs the Lorenz batch path, 16 trajectories
+    ln, lt = POLY_SYSTEMS["lorenz"]
+    q = mpts.Poly(ln, lt, K=E["K"], N=E["N"])
+    lor = mpts.Lorenz(K=E["K"], N=E["N"])
+    xs = [[lor.from_str(v) for v in x] for x in poly_states(7, 16, "lorenz")]
+    q.integrate(xs, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    q.integrate(xs, n)
+    tq = time.perf_counter() - t0
+    mpts.integrate_batch([lor] * 16, xs, [n] * 16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mpts.integrate_batch([lor] * 16, xs, [n] * 16)
+    tl = time.perf_counter() - t0
+    out["lorenz_terms_x16"] = {"poly_s": tq, "lorenz_batch_s": tl, "poly_over_lorenz": tq / tl}
+    print(json.dumps(out), flush=True)
+
+
 def run_peak():
     """Measured issue rates of the two arithmetic units (registers only)."""
     from paper_1908_09301_amd import mpts
@@ -314,7 +361,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--wgs", type=int, default=0, help="workgroups per trajectory (0: all CUs)")
     ap.add_argument("--workload", default="lorenz_k4000_n3500", choices=sorted(SINGLE))
-    ap.add_argument("--mode", default="single", choices=["single", "adjoint", "batch", "peak"])
+    ap.add_argument("--mode", default="single", choices=["single", "adjoint", "batch", "peak", "poly"])
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -329,6 +376,8 @@ def main():
         run_adjoint(args)
     elif args.mode == "batch":
         run_batch(args)
+    elif args.mode == "poly":
+        run_poly(args)
     elif args.mode == "peak":
         run_peak()
     else:
