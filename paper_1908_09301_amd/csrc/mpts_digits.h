@@ -189,6 +189,24 @@ __device__ __forceinline__ int digit_at(const int (&d)[C], int k) {
   return __builtin_amdgcn_readlane(v, kl);
 }
 
+// Whether bits [a, b) of D (0 <= a < b, uniform) are all zeros or all ones
+// (uniform).
+template <int C>
+__device__ __forceinline__ bool bits_uniform(const int (&d)[C], int a, int b) {
+  const int k0 = lane_id() * C;
+  bool any0 = false, any1 = false;
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const int lo = (k0 + j) * DBITS;  // bit index of the digit's bit 0
+    const int s = min(max(a - lo, 0), DBITS), e = min(max(b - lo, 0), DBITS);
+    const uint32_t mask = e > s ? ((1u << (e - s)) - 1u) << s : 0u;
+    const uint32_t x = (uint32_t)d[j];
+    any1 |= (x & mask) != 0u;
+    any0 |= (~x & mask) != 0u;
+  }
+  return __ballot(any0) == 0ull || __ballot(any1) == 0ull;
+}
+
 // Round sign * D * 2^(28 base) to p = 32 L bits (nearest, ties to even;
 // sticky_in: a nonzero value below D) and write it as a row into the LDS
 // row `row` (RS words).  D must have a zero top digit (room for the carry of

@@ -305,37 +305,100 @@ struct TauQ {
   int n, m0, m1, e, dv;
 };
 
+// Columns [lo, lo + 64 Ct) of the numerator n h + m 2^(28 e) h + d c of a
+// rational Horner step into registers (lane l: columns lo + l Ct + j).
+// Rows carry RPAD >= Ct + 1 zero digits on each side (and a zero row has
+// zero digits): a chunk that overlaps a row's digits is read whole, one
+// that does not is pointed at the zeros, so no read is predicated.
+template <int Ct>
+__device__ __forceinline__ void tau_gather(const TauQ &q, const l_i32 *h, int eh, const l_i32 *c,
+                                           int ec, long long lo, int nd, long long (&v)[Ct]) {
+  const int lane = lane_id();
+  const l_i32 *hd = h + HDR + RPAD;
+  int kh = (int)(lo - eh) + lane * Ct;
+  int km = kh - q.e;
+  kh = min(max(kh, -Ct), nd);
+  km = min(max(km, -Ct), nd + 1);
+#pragma unroll
+  for (int j = 0; j < Ct; ++j)
+    v[j] = (long long)q.n * hd[kh + j] + (long long)q.m0 * hd[km + j] +
+           (long long)q.m1 * hd[km + j - 1];
+  if (c) {
+    const l_i32 *cd = c + HDR + RPAD;
+    int kc = (int)(lo - ec) + lane * Ct;
+    kc = min(max(kc, -Ct), nd);
+#pragma unroll
+    for (int j = 0; j < Ct; ++j) v[j] += (long long)q.dv * cd[kc + j];
+  }
+}
+
 // One step h <- round(tau h + c) of equation (2) for a rational step size
 // (c: an LDS row, or null for h <- round(tau h)), in place on the LDS row
-// h.  The exact value tau h + c is (n h + m 2^(28 e) h + d c) / d: the
-// numerator's columns are gathered straight into registers (each a sum of
-// four digit multiples, |v| < 2^57), resolved, divided by d in registers and
-// rounded once.  A numerator with fewer than p + 15 bits above its lowest
-// column (cancellation) goes through div_to_row, which extends it with zero
-// digits.  Single wavefront; scratch: 64 CM LDS digits.
+// h.  The exact value tau h + c is (n h + m 2^(28 e) h + d c) / d.
+//
+// First try: the numerator's columns from G = 3 digits below its lowest
+// operand (about half the columns: the m term lies about p bits below n h).
+// Its columns below that window add, in units of the window's lowest
+// column, less than 2^30 in magnitude (each column sum is below 2^57), so
+// the quotient q of the truncated numerator is within 2^31 of the exact
+// one.  When q's bits from 2^31 up to the one below its round bit are
+// neither all zeros nor all ones, the exact quotient has the same kept bits
+// and round bit and a nonzero remainder, so q rounded with sticky set is
+// the correctly rounded result.  Otherwise (or on cancellation) the whole
+// numerator is gathered: resolved, divided by d in registers and rounded
+// once, or through div_to_row when it is too short for p + 2 quotient bits.
+// Single wavefront; scratch: 64 CM LDS digits.
 template <int CM, typename Mark>
 __device__ __forceinline__ bool tau_step_rational(const TauQ &q, int L, int nd, int RS, int32_t *h_,
                                                   const int32_t *c_, int32_t *scratch,
                                                   uint32_t *err, Mark &&mark) {
   const int lane = lane_id();
   const l_i32 *h = (const l_i32 *)h_;
+  const l_i32 *c = (const l_i32 *)c_;
   const int eh = h[0], sh = h[1];
-  const int ec = c_ ? ((const l_i32 *)c_)[0] : 0, sc = c_ ? ((const l_i32 *)c_)[1] : 0;
+  const int ec = c ? c[0] : 0, sc = c ? c[1] : 0;
   const bool mterm = q.m0 != 0 || q.m1 != 0;
   // window: the m term lies about p bits below n h; without it, one zero
   // digit below the lowest operand keeps p + 2 quotient bits
-  long long lo = 1LL << 40, hi = -(1LL << 40);
+  long long lo = 1LL << 40, hi = -(1LL << 40), lop = 1LL << 40;
   if (sh != 0) {
     lo = mterm ? (long long)eh + q.e : (long long)eh - 1;
+    lop = eh;
     hi = (long long)eh + nd + 1;  // n h: |n| < 2^27 adds one digit
     if (mterm) hi = max(hi, (long long)eh + q.e + nd + 1);
   }
   if (sc != 0) {
     lo = min(lo, (long long)ec - 1);
+    lop = min(lop, (long long)ec);
     hi = max(hi, (long long)ec + nd + 1);
   }
-  int C = 2;
   bool ok = true;
+  // the truncated window
+  bool done = false;
+  constexpr int G = 3;
+  if (lo <= hi && hi - (lop - G) + 2 <= 64LL * CM) {
+    const long long lot = lop - G;
+    const int Wt = (int)(hi - lot + 2);
+    with_chunks<CM>(Wt > 128 ? (Wt + 63) >> 6 : 2, [&](auto ct) {
+      constexpr int Ct = decltype(ct)::value;
+      long long v[Ct];
+      tau_gather<Ct>(q, h, eh, c, ec, lot, nd, v);
+      int d[Ct];
+      bool ovf = false;
+      const int sgn = resolve_c<Ct>(v, d, &ovf);
+      mark(13);
+      if (sgn == 0 || ovf) return;
+      (void)div_small_c<Ct>(d, q.dv);
+      const int B = top_bit_c<Ct>(d);
+      const int rb = B + 1 - 32 * L - 1;  // the round bit
+      if (rb < 40 || bits_uniform<Ct>(d, 31, rb)) return;
+      ok &= round_to_row<Ct>(d, sgn, lot, true, L, nd, RS, h_);
+      done = true;
+      mark(14);
+    });
+  }
+  if (done) return ok;
+  int C = 2;
   if (lo > hi) {
     lo = 0;
   } else if (hi - lo + 2 > 64LL * CM) {
@@ -352,32 +415,11 @@ __device__ __forceinline__ bool tau_step_rational(const TauQ &q, int L, int nd, 
     long long v[Ct];
 #pragma unroll
     for (int j = 0; j < Ct; ++j) v[j] = 0;
-    if (any) {
-      // rows carry RPAD >= Ct + 1 zero digits on each side (and a zero row
-      // has zero digits): a chunk that overlaps the digits is read whole,
-      // one that does not is pointed at the zeros, so no read is predicated
-      const l_i32 *hd = h + HDR + RPAD;
-      int kh = (int)(lo - eh) + lane * Ct;
-      int km = kh - q.e;
-      kh = min(max(kh, -Ct), nd);
-      km = min(max(km, -Ct), nd + 1);
-#pragma unroll
-      for (int j = 0; j < Ct; ++j)
-        v[j] = (long long)q.n * hd[kh + j] + (long long)q.m0 * hd[km + j] +
-               (long long)q.m1 * hd[km + j - 1];
-      if (c_) {
-        const l_i32 *cd = (const l_i32 *)c_ + HDR + RPAD;
-        int kc = (int)(lo - ec) + lane * Ct;
-        kc = min(max(kc, -Ct), nd);
-#pragma unroll
-        for (int j = 0; j < Ct; ++j) v[j] += (long long)q.dv * cd[kc + j];
-      }
-    }
+    if (any) tau_gather<Ct>(q, h, eh, c, ec, lo, nd, v);
     int d[Ct];
     bool ovf = false;
     const int sgn = resolve_c<Ct>(v, d, &ovf);
     if (ovf && lane == 0) atomicOr(err, 1u | 64u);
-    mark(13);
     const int B = sgn != 0 ? top_bit_c<Ct>(d) : -1;
     if (B >= 32 * L + 15) {
       const bool sticky = div_small_c<Ct>(d, q.dv);
