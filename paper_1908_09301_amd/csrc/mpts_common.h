@@ -117,5 +117,9 @@ struct PolyInst {
 enum { PH_SETUP = 0, PH_ACCUM, PH_FLUSH, PH_WAIT, PH_FINAL, PH_CLEAR, PH_HORNER, PH_STEP0,
        PH_EBUILD, PH_ESETUP = 10, PH_NPHASE = 16 };
 constexpr int PROF_RANK = 8;  // per-workgroup profile words
+// leader slot of the lag from the last arrival to the end of the leader's
+// wait, and the word holding the latest arrival time (in the first
+// follower's per-workgroup words)
+enum { PH_ARRLAG = 10, PROF_ARRT = 2 * PH_NPHASE + PROF_RANK + 7 };
 
 }  // namespace mpts

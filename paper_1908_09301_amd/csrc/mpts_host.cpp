@@ -711,7 +711,7 @@ int read_status(mpts_ctx *c, void *ws, hipStream_t s) {
       (void)hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev);
       double us = rate > 0 ? 1e3 / rate : 0.0;  // rate in kHz
       static const char *nm[16] = {"setup", "accum", "flush", "wait", "final", "release", "horner",
-                                   "step0", "spare", "f.round1", "f.res2", "f.div", "f.row", "h.prod", "h.div", "h.round"};
+                                   "step0", "spare", "f.round1", "arrlag", "f.div", "f.row", "h.prod", "h.div", "h.round"};
       fprintf(stderr, "mpts phases (us):");
       for (int w2 = 0; w2 < 2; ++w2) {
         fprintf(stderr, w2 ? "\n  wg1:" : "\n  leader:");
@@ -727,14 +727,31 @@ int read_status(mpts_ctx *c, void *ws, hipStream_t s) {
       std::vector<unsigned long long> pr((size_t)G * PROF_RANK);
       if (G > 0 && hipMemcpy(pr.data(), (char *)ws + l.prof + 2 * PH_NPHASE * 8, pr.size() * 8,
                              hipMemcpyDeviceToHost) == hipSuccess) {
-        static const char *rn[4] = {"setup", "accum", "flush", "release"};
-        for (int q = 0; q < 4; ++q) {
+        static const char *rn[5] = {"setup", "accum", "flush", "release", "final"};
+        static const int rs[5] = {0, 1, 2, 3, 6};
+        for (int q = 0; q < 5; ++q) {
           std::vector<std::pair<double, int>> v;
-          for (int r = 0; r < G; ++r) v.push_back({pr[(size_t)r * PROF_RANK + q] * us, r});
+          for (int r = 0; r < G; ++r) v.push_back({pr[(size_t)r * PROF_RANK + rs[q]] * us, r});
           std::sort(v.begin(), v.end());
           fprintf(stderr, "  per-wg %s: min %.1f (wg %d) med %.1f max %.1f (wg %d) p90 %.1f\n", rn[q],
                   v[0].first, v[0].second, v[G / 2].first, v[G - 1].first, v[G - 1].second,
                   v[(G * 9) / 10].first);
+          if (q == 4 && G > 8) {
+            // the slowest followers' (xcc, se/cu) places
+            fprintf(stderr, "  slowest final:");
+            for (int k = G - 1; k >= G - 6 && k >= 1; --k) {
+              const int r = v[k].second;
+              const unsigned x = (unsigned)pr[(size_t)r * PROF_RANK + 4], hw = (unsigned)pr[(size_t)r * PROF_RANK + 5];
+              fprintf(stderr, " wg%d %.1f (xcc %u hw 0x%x)", r, v[k].first, x, hw);
+            }
+            fprintf(stderr, "\n  fastest final:");
+            for (int k = 1; k <= 5 && k < G; ++k) {
+              const int r = v[k].second;
+              const unsigned x = (unsigned)pr[(size_t)r * PROF_RANK + 4], hw = (unsigned)pr[(size_t)r * PROF_RANK + 5];
+              fprintf(stderr, " wg%d %.1f (xcc %u hw 0x%x)", r, v[k].first, x, hw);
+            }
+            fprintf(stderr, "\n");
+          }
         }
         std::map<unsigned, int> cu;
         int xcc_ok = 0;

@@ -545,7 +545,12 @@ __device__ __forceinline__ void prof_mark(const Inst &I, const Carve &cv, int ph
   const unsigned long long t = wall_clock64();
   const unsigned long long dt = t - *cv.tmark;
   if (rank <= 1) atomicAdd(I.prof + rank * PH_NPHASE + ph, dt);
-  const int slot = ph == PH_SETUP ? 0 : ph == PH_ACCUM ? 1 : ph == PH_FLUSH ? 2 : ph == PH_CLEAR ? 3 : -1;
+  const int slot = ph == PH_SETUP    ? 0
+                   : ph == PH_ACCUM ? 1
+                   : ph == PH_FLUSH ? 2
+                   : ph == PH_CLEAR ? 3
+                   : ph == PH_FINAL ? 6
+                                    : -1;
   if (slot >= 0) atomicAdd(I.prof + 2 * PH_NPHASE + rank * PROF_RANK + slot, dt);
   *cv.tmark = t;
 }
@@ -854,6 +859,7 @@ __device__ void release_rows(const Inst &I, const Carve &cv, bool leader,
                          ((unsigned long long)gs.gen << 32) | (uint32_t)v, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
     }
+
     if (tid < 3) {
       const int task = tid == 0 ? 2 : tid - 1;
       const l_i32 *row = (const l_i32 *)(cv.trow + (size_t)(2 * task + 1) * RS);
@@ -1168,6 +1174,9 @@ __device__ __forceinline__ void late_step(const Inst &I, const Carve &cv, int ra
   if (tid == 0)
     __hip_atomic_fetch_add(I.sync + SY_ARRIVE + 32 * (rank % NSPLIT), 1u, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
+  if (I.prof && tid == 0)  // the latest arrival time of the index (phase timers)
+    __hip_atomic_fetch_max(I.prof + PROF_ARRT, wall_clock64(), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
   prof_mark(I, cv, PH_FLUSH);
 }
 
@@ -1389,6 +1398,14 @@ __device__ void forward_coefficients(const Inst &I, const Carve &cv, int rank, G
       gs.arrived += (unsigned long long)(I.G - 1);
       if (tid < 64) spin_until_sum(I.sync + SY_ARRIVE, (uint32_t)gs.arrived, err);
       __syncthreads();
+      if (I.prof && tid == 0) {
+        // from the last arrival to the end of this wait
+        const unsigned long long t = wall_clock64();
+        const unsigned long long a = __hip_atomic_load(I.prof + PROF_ARRT, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+        if (a != 0 && t > a) atomicAdd(I.prof + PH_ARRLAG, t - a);
+        __hip_atomic_store(I.prof + PROF_ARRT, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
       prof_mark(I, cv, PH_WAIT);
       const long long *frames = I.gframes + (size_t)(gs.nbulk & 1) * NFR * WB;
       if (wave < 3) finalize_task<CM>(I, cv, wave, i, frames, true, err);
