@@ -584,32 +584,16 @@ int make_ctx(const char *sigma, const char *R, const char *b, int L, int N, cons
   return MPTS_OK;
 }
 
-// Modelled milliseconds per step of one trajectory on G workgroups: the
-// serial latency per coefficient index (one workgroup, or a group that has
-// to synchronise) plus the product work spread over the group.
+// Modelled milliseconds per step of one trajectory on G workgroups (the
+// batch planner's estimate for sizes it has not timed): the serial latency
+// per coefficient index plus the product work spread over the group.  The
+// latencies are measured at K=100/N=40, where the work is negligible: 1.09
+// ms per step on one workgroup, about 0.7 on groups of 8 to 256.
 double model_ms(const mpts_ctx *c, int G) {
-  // latency per coefficient index (single workgroup / group synchronisation)
-  // plus the product work spread over G workgroups
-  const double lat = G == 1 ? 0.012 : 0.045;
+  const double lat = G == 1 ? 0.0136 : 0.0088;
   const double digit_macs = (double)c->N * (c->N + 5) * c->nd * (double)c->nd;
   const double wg_rate = 2.6e13 / 256.0 * 0.25;  // sustained digit-MAC/s of one workgroup
   return (c->N * 2 * lat) + digit_macs / (G * wg_rate) * 1e3;
-}
-
-// Workgroups for one trajectory when the caller sets none: the power of two
-// (up to the compute-unit count) with the smallest modelled step time.
-int default_groups(const mpts_ctx *c) {
-  int best = 1;
-  double tb = model_ms(c, 1);
-  for (int g = 2; g <= c->cus; g *= 2) {
-    double t = model_ms(c, g);
-    if (t < tb) {
-      tb = t;
-      best = g;
-    }
-  }
-  if (best * 2 > c->cus && model_ms(c, c->cus) <= tb) best = c->cus;
-  return best;
 }
 
 int run_single(mpts_ctx *c, int mode, long long nsteps, const void *x0_dev, void *xout_dev,
@@ -1965,7 +1949,7 @@ int mpts_grad_batch(mpts_ctx *const *ctxs, int32_t count, const mpts_bf *x0, con
   std::vector<int> G((size_t)count);
   int total = 0;
   for (int t = 0; t < count; ++t) {
-    G[t] = std::max(1, std::min(ctxs[t]->wgs > 0 ? ctxs[t]->wgs : default_groups(ctxs[t]), share));
+    G[t] = std::max(1, std::min(ctxs[t]->wgs > 0 ? ctxs[t]->wgs : share, share));
     total += G[t];
   }
   char *base = (char *)ws;
