@@ -132,3 +132,37 @@ def test_error_paths_before_any_device_work():
     st = lib.mpts_grad(p.handle, x.ptr(), 1, 7, g, None, None, None, ctypes.c_void_p(1 << 20),
                        need, None)
     assert st == mpts.MPTS_EINVAL
+
+
+def test_polynomial_systems_are_checked_on_the_host():
+    """mpts_poly_create refuses bad terms and sizes and systems past its
+    limits before any device work; a system's coefficients parse exactly
+    like the oracle's."""
+    from oracle.bigfloat import parse
+    from workloads import POLY_SYSTEMS
+    mpts = _lib()
+    nvar, terms = POLY_SYSTEMS["rossler"]
+    p = mpts.Poly(nvar, terms, L=4, N=10)
+    for text in ("0.2", "-5.7", "1/3"):
+        assert p.from_str(text) == tuple(parse(text, p.p))
+    bad = [
+        (3, [(3, "1", 0, -1)]),        # equation out of range
+        (3, [(0, "1", 3, -1)]),        # variable out of range
+        (3, [(0, "1", -1, 1)]),        # w without u
+        (3, [(0, "x", 0, -1)]),        # not a number
+        (0, []),                       # no variable
+    ]
+    for nv, ts in bad:
+        with pytest.raises(mpts.MptsError) as ei:
+            mpts.Poly(nv, ts, L=4, N=10)
+        assert ei.value.code == mpts.MPTS_EINVAL, (nv, ts)
+    limits = [
+        (5, [(0, "1", 0, -1)]),                                                  # five variables
+        (4, [(0, "1", u, w) for u in range(4) for w in range(u, 4)][:6]),        # six product pairs
+        (1, [(0, "1", -1, -1), (0, "2", -1, -1)]),                               # two constants
+        (2, [(0, c, 0, -1) for c in ("2", "3", "5", "7", "11")]),                # five non-unit products
+    ]
+    for nv, ts in limits:
+        with pytest.raises(mpts.MptsError) as ei:
+            mpts.Poly(nv, ts, L=4, N=10)
+        assert ei.value.code == mpts.MPTS_EUNSUPPORTED, (nv, ts)
